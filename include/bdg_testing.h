@@ -1,0 +1,39 @@
+/*
+ * bdg_testing.h - kernel-level entry points of the library, exported for parity tests of
+ * the dense building blocks of the subspace iteration (Section 3.2: Gram matrices of the
+ * bi-orthogonal Gram-Schmidt and Rayleigh-Ritz steps, basis updates, projected problems).
+ * Same conventions as bdg.h: device pointers, column-major complex128 (interleaved re, im),
+ * synchronous on the context stream, bdg_status return codes.  They need a context only
+ * for its stream and scratch memory (no ground state).
+ */
+#ifndef BDG_TESTING_H
+#define BDG_TESTING_H
+
+#include "bdg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C (m1 x m2, ldc) = alpha * A^H B with A: K x m1 (column stride lda), B: K x m2 (ldb), on
+ * the FP64 matrix cores with a deterministic split-K reduction.  hermitian = 1 requires
+ * A == B and fills C from its upper triangle. */
+bdg_status bdg_test_gram(bdg_ctx* ctx, long long K, int m1, int m2, const void* A, long long lda,
+                         const void* B, long long ldb, double alpha, void* C, int ldc, int hermitian);
+
+/* Y (K x nb, ldy) = S (K x m, lds) * Cm (m x nb, ldcm) + beta * Y on the FP64 matrix cores. */
+bdg_status bdg_test_update(bdg_ctx* ctx, long long K, int m, const void* S, long long lds,
+                           const void* Cm, int ldcm, int nb, double beta, void* Y, long long ldy);
+
+/* One-sided Jacobi SVD of G (rows x m, ldg), m <= 512: G is replaced by U diag(s) with
+ * columns ordered by descending s; V (m x m, ldv) receives V; s (device, m). */
+bdg_status bdg_test_svd(bdg_ctx* ctx, int rows, int m, void* G, int ldg, void* V, int ldv, void* s);
+
+/* In-place lower Cholesky A = L L^H of an m x m Hermitian matrix (upper triangle zeroed);
+ * returns BDG_EBREAKDOWN when a pivot is not positive. */
+bdg_status bdg_test_cholesky(bdg_ctx* ctx, int m, void* A, int lda);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDG_TESTING_H */

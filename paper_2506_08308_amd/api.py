@@ -1,0 +1,190 @@
+"""Thin Python binding of the C ABI: torch tensors provide device memory and the stream.
+
+Every call forwards to libbdg.so; no step of the method runs in Python or on the CPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import enum
+from typing import Optional, Sequence
+
+from . import _lib
+
+
+class BdgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+
+
+class Precision(enum.IntEnum):
+    FP64 = _lib.BDG_FP64
+    FP32_APPLY = _lib.BDG_FP32_APPLY
+
+
+class Form(enum.IntEnum):
+    UV = _lib.BDG_FORM_UV
+    FG = _lib.BDG_FORM_FG
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class BdgContext:
+    """One problem (grid, box, V, beta_n, beta_s, mass, magnetization, precision) on the GPU.
+
+    ``n`` and ``L`` are ordered (x, y, z); ``V`` is a float64 device tensor of shape
+    ``(Nz, Ny, Nx)[-dim:]`` (x fastest).
+    """
+
+    def __init__(self, dim: int, n: Sequence[int], L: Sequence[float], V, beta_n: float, beta_s: float,
+                 mass: float = 1.0, magnetization: float = 0.0, precision: Precision = Precision.FP64,
+                 stream=None):
+        torch = _torch()
+        self._lib = _lib.load()
+        self.dim = int(dim)
+        self.n = tuple(int(v) for v in n)[:dim]
+        self.L = tuple(float(v) for v in L)[:dim]
+        self.npts = 1
+        for v in self.n:
+            self.npts *= v
+        self.precision = Precision(precision)
+        self.grid_shape = tuple(reversed(self.n))
+        self.device = V.device
+        self._V = V.to(torch.float64).contiguous()
+        pr = _lib.Problem()
+        pr.dim = self.dim
+        for a in range(3):
+            pr.n[a] = self.n[a] if a < dim else 1
+            pr.L[a] = self.L[a] if a < dim else 1.0
+        pr.beta_n, pr.beta_s = float(beta_n), float(beta_s)
+        pr.mass, pr.magnetization = float(mass), float(magnetization)
+        pr.precision = int(self.precision)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self._lib.bdg_create(ctypes.byref(pr), ctypes.c_void_p(_ptr(self._V)),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != _lib.BDG_OK:
+            raise BdgError(st, "bdg_create failed")
+        self._h = h
+        self.h = tuple(2.0 * Li / ni for Li, ni in zip(self.L, self.n))
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st: int, what: str):
+        if st != _lib.BDG_OK:
+            msg = self._lib.bdg_last_error(self._h)
+            raise BdgError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bdg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def vector_dtype(self):
+        torch = _torch()
+        return torch.complex64 if self.precision == Precision.FP32_APPLY else torch.complex128
+
+    # ------------------------------------------------------------------ API
+    def ground_state(self, phi0=None, tol: float = 1e-12, max_iter: int = 200000, check: bool = True):
+        """Normalized gradient flow on the device; returns (phi, mu, residual, iters)."""
+        torch = _torch()
+        phi = torch.empty((3,) + self.grid_shape, dtype=torch.float64, device=self.device)
+        mu = (ctypes.c_double * 3)()
+        res = ctypes.c_double()
+        its = ctypes.c_int()
+        p0 = None if phi0 is None else phi0.to(torch.float64).contiguous()
+        st = self._lib.bdg_ground_state(self._h, ctypes.c_void_p(_ptr(p0)), tol, max_iter,
+                                        ctypes.c_void_p(_ptr(phi)), mu, ctypes.byref(res), ctypes.byref(its))
+        if check:
+            self._check(st, "bdg_ground_state")
+        return phi, [mu[0], mu[1], mu[2]], res.value, its.value
+
+    def set_ground_state(self, phi, mu):
+        torch = _torch()
+        self._phi = phi.to(device=self.device, dtype=torch.float64).contiguous()
+        m = (ctypes.c_double * 3)(*[float(v) for v in mu])
+        self._check(self._lib.bdg_set_ground_state(self._h, ctypes.c_void_p(_ptr(self._phi)), m),
+                    "bdg_set_ground_state")
+
+    def apply(self, X, form: Form = Form.FG, transpose: bool = False, out=None):
+        """Y = H X for a block X of shape (b, 6, *grid) (complex128, or complex64 in FP32_APPLY)."""
+        torch = _torch()
+        if X.dtype != self.vector_dtype():
+            raise ValueError(f"expected {self.vector_dtype()}")
+        if X.shape[-len(self.grid_shape):] != self.grid_shape or X.shape[-self.dim - 1] != 6:
+            raise ValueError("expected shape (b, 6, *grid)")
+        nvec = X.numel() // (6 * self.npts)
+        Y = torch.empty_like(X) if out is None else out
+        self._check(self._lib.bdg_apply(self._h, int(form), int(bool(transpose)), nvec,
+                                        ctypes.c_void_p(_ptr(X)), ctypes.c_void_p(_ptr(Y))), "bdg_apply")
+        return Y
+
+    def biortho(self, F, G):
+        """In-place bi-orthogonalization of F, G (nvec, 3, *grid) complex128; returns (sigma, rank)."""
+        nvec = F.shape[0]
+        sig = (ctypes.c_double * nvec)()
+        rank = ctypes.c_int()
+        self._check(self._lib.bdg_biortho(self._h, nvec, ctypes.c_void_p(_ptr(F)), ctypes.c_void_p(_ptr(G)),
+                                          sig, ctypes.byref(rank)), "bdg_biortho")
+        return list(sig), rank.value
+
+    def eigs(self, k: int, block: int, tol: float = 1e-8, max_iter: int = 2000, X0=None, seed: int = 0,
+             want_vectors: bool = True, check: bool = True):
+        """k smallest positive omega; returns dict(omega, uv, residual, iters, status)."""
+        torch = _torch()
+        om = (ctypes.c_double * k)()
+        res = (ctypes.c_double * k)()
+        its = ctypes.c_int()
+        uv = torch.empty((k, 6) + self.grid_shape, dtype=torch.complex128, device=self.device) \
+            if want_vectors else None
+        x0 = None
+        if X0 is not None:
+            x0 = X0.to(device=self.device, dtype=torch.complex128).contiguous()
+        st = self._lib.bdg_eigs(self._h, k, block, tol, max_iter, ctypes.c_void_p(_ptr(x0)), seed, om,
+                                ctypes.c_void_p(_ptr(uv)), res, ctypes.byref(its))
+        if check:
+            self._check(st, "bdg_eigs")
+        return {"omega": list(om), "uv": uv, "residual": list(res), "iters": its.value, "status": st}
+
+    def eigs_grad(self, omega, uv):
+        """d omega_j / d V(x) (k, *grid), d omega_j / d beta_n, d omega_j / d beta_s."""
+        torch = _torch()
+        k = len(omega)
+        om = (ctypes.c_double * k)(*omega)
+        dV = torch.empty((k,) + self.grid_shape, dtype=torch.float64, device=self.device)
+        dbn = (ctypes.c_double * k)()
+        dbs = (ctypes.c_double * k)()
+        self._check(self._lib.bdg_eigs_grad(self._h, k, om, ctypes.c_void_p(_ptr(uv.contiguous())),
+                                            ctypes.c_void_p(_ptr(dV)), dbn, dbs), "bdg_eigs_grad")
+        return dV, list(dbn), list(dbs)
+
+    def stats(self):
+        out = (ctypes.c_double * 10)()
+        self._check(self._lib.bdg_stats(self._h, out, 10), "bdg_stats")
+        keys = ["total_ms", "apply_ms", "precond_ms", "gram_ms", "small_ms", "update_ms", "setup_ms",
+                "iters", "applies_fp64", "applies_fp32"]
+        return dict(zip(keys, list(out)))

@@ -1,0 +1,157 @@
+// Internal declarations shared by the library's HIP sources (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bdg.h"
+
+// ------------------------------------------------------------------------------------
+// Complex helpers (interleaved re, im in HIP vector types)
+// ------------------------------------------------------------------------------------
+template <typename R> struct cplx_of;
+template <> struct cplx_of<double> { using type = double2; };
+template <> struct cplx_of<float> { using type = float2; };
+
+template <typename V> __host__ __device__ __forceinline__ V cmk(decltype(V::x) a, decltype(V::x) b) {
+    V r; r.x = a; r.y = b; return r;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return cmk<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return cmk<V>(a.x - b.x, a.y - b.y); }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    return cmk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+    return cmk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename V> __device__ __forceinline__ V cscale(V a, decltype(V::x) s) { return cmk<V>(a.x * s, a.y * s); }
+
+// ------------------------------------------------------------------------------------
+// Context
+// ------------------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct bdg_ctx {
+    bdg_problem prob{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int dim = 1;
+    int n[3] = {1, 1, 1};
+    double L[3] = {1, 1, 1};
+    double h[3] = {1, 1, 1};
+    double hd = 1.0;              // h_x h_y h_z (weight of the discrete inner product)
+    long long npts = 1;           // grid points
+    // device tables
+    double* V = nullptr;          // npts
+    double* phi = nullptr;        // 3 npts (ground state)
+    double mu[3] = {0, 0, 0};
+    bool has_gs = false;
+    double* coef64 = nullptr;     // 12 npts: H_+ (6 sym entries) then H_- (6), V - mu folded in
+    float* coef32 = nullptr;      // same, rounded
+    double2* tw64[3] = {nullptr, nullptr, nullptr};   // exp(-2 pi i m / N_a), m < N_a
+    float2* tw32[3] = {nullptr, nullptr, nullptr};
+    double* sym64[3] = {nullptr, nullptr, nullptr};   // mu_m^2 / 2 per axis, FFT order
+    float* sym32[3] = {nullptr, nullptr, nullptr};
+    // scratch owned by the context (grown on demand)
+    DevBuf scratch[8];
+    std::string err;
+    double stats[10] = {0};
+    std::vector<void*> owned;     // every hipMalloc of the context, freed in destroy
+};
+
+// status helpers
+bdg_status ctx_fail(bdg_ctx* c, bdg_status s, const std::string& msg);
+bdg_status hip_check(bdg_ctx* c, hipError_t e, const char* what);
+#define BDG_HIP(ctx, ...)                                               \
+    do {                                                                \
+        hipError_t e_ = (__VA_ARGS__);                                  \
+        if (e_ != hipSuccess) return hip_check((ctx), e_, #__VA_ARGS__); \
+    } while (0)
+#define BDG_TRY(...)                                                    \
+    do {                                                                \
+        bdg_status s_ = (__VA_ARGS__);                                  \
+        if (s_ != BDG_OK) return s_;                                    \
+    } while (0)
+
+bdg_status ctx_alloc(bdg_ctx* c, void** p, size_t bytes);
+void ctx_free(bdg_ctx* c, void* p);
+// scratch slot i with at least `bytes` (contents undefined)
+bdg_status ctx_scratch(bdg_ctx* c, int slot, size_t bytes, void** out);
+
+// ------------------------------------------------------------------------------------
+// Operator kernels (fft_apply.hip)
+// ------------------------------------------------------------------------------------
+// Where the six fields (f_1, f_0, f_-1, g_1, g_0, g_-1) of vector j live:
+// half 0 (f or u) at lo + j * vstride + c * npts, half 1 (g or v) at hi + j * vstride + c * npts.
+template <typename V> struct BlockRef {
+    V* lo;
+    V* hi;
+    long long vstride;
+};
+
+// Y = H X for nvec vectors; form BDG_FORM_FG or BDG_FORM_UV; transpose selects the adjoint.
+template <typename R>
+bdg_status launch_apply(bdg_ctx* c, int form, int transpose, int nvec,
+                        BlockRef<const typename cplx_of<R>::type> X, BlockRef<typename cplx_of<R>::type> Y);
+
+// Y = T X with T = (|k|^2/2 + shift)^-1 on `nfields` complex grid fields;
+// field f at base + (f / fpv) * vstride + (f % fpv) * npts.  X and Y may alias.
+template <typename R>
+bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, double shift);
+
+// Y = F^-1 m(k) F X with m = |k|^2/2 (precond = 0) or (|k|^2/2 + shift)^-1 (precond = 1).
+template <typename R>
+bdg_status launch_fourier(bdg_ctx* c, int nfields, int fpv, long long vstride,
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, int precond, double shift);
+
+// Plain forward/inverse (unnormalized) d-dimensional FFT of nfields fields (tests, ground state).
+template <typename R>
+bdg_status launch_fft(bdg_ctx* c, int nfields, const typename cplx_of<R>::type* X,
+                      typename cplx_of<R>::type* Y, int inverse);
+
+// coefficient fields of H_+ and H_- from the ground state (capi)
+bdg_status build_coefficients(bdg_ctx* c);
+
+// ------------------------------------------------------------------------------------
+// Dense kernels (dense.hip)
+// ------------------------------------------------------------------------------------
+// C (m1 x m2, column-major, ldc) = alpha * A^H B, A: K x m1 complex (column stride lda,
+// elements in TA), B: K x m2 (ldb, TB).  hermitian != 0: A == B and only needed once
+// (C is completed from its upper triangle).  Deterministic split-K reduction.
+struct Seg {
+    const void* p;
+    int ncols;
+};
+// Gram with column segments (logical column order = segment order), same column stride.
+bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long lda, const Seg* sb, int nb_,
+                    long long ldb, double alpha, double2* C, int ldc, int hermitian);
+template <typename TA, typename TB>
+bdg_status gram(bdg_ctx* c, long long K, int m1, int m2, const TA* A, long long lda,
+                const TB* B, long long ldb, double alpha, double2* C, int ldc, int hermitian);
+
+// Y (K x nb) = S (K x m) Cm (m x nb) + beta * Y.  S columns: segments (ptr, ncols) with
+// column stride lds each; Cm device m x nb column-major (ldcm); Y column stride ldy.
+bdg_status update(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds,
+                  const double2* Cm, int ldcm, int nb, double beta, double2* Y, long long ldy);
+
+// small dense FP64 complex matrices on the device (column-major)
+bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, double2 alpha,
+                      const double2* A, int lda, const double2* B, int ldb, double2 beta,
+                      double2* C, int ldc);
+// in-place lower Cholesky (upper part zeroed); *info_dev = 0 ok, j+1 if the j-th pivot fails
+bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev);
+// one-sided Jacobi SVD: G (rows x m) -> G V = U diag(s); G overwritten by U diag(s) (columns),
+// V (m x m) receives V, s (m, device) the column norms; columns sorted by descending s.
+bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s);
+
+// column norms squared (deterministic), etc.
+bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx,
+                    double* out_dev);

@@ -1,0 +1,586 @@
+// Dense linear algebra of the subspace iteration on gfx950 (Section 3.2): the Gram
+// matrices X^H Y of the bi-orthogonal Gram-Schmidt and Rayleigh-Ritz steps and the basis
+// updates S C run on the FP64 matrix cores (v_mfma_f64_16x16x4f64); the small projected
+// problems (m <= 512) use single-workgroup FP64 kernels (Cholesky, one-sided Jacobi SVD)
+// and a plain small GEMM.  Complex numbers are interleaved (re, im) doubles.
+//
+// MFMA operand layout (16x16x4 f64, wave64; checked on the device): lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator register r of lane l holds D[4 r + l / 16][l % 16].
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ----------------------------------------------------------------------------------------
+// Gram: part[s] = A^H B over the K-range of split s, tile 64 x 64 per workgroup (4 waves of
+// 32 x 32).  The real form uses the interleaved doubles as 2K real rows:
+//   Re C = a^T b,  Im C = a^T b'  with b'[2k] = Im B[k], b'[2k+1] = -Re B[k].
+// ----------------------------------------------------------------------------------------
+struct SegList {
+    const double2* p[4];
+    int start[5];
+    int nseg;
+};
+
+__device__ __forceinline__ const double2* seg_col(const SegList& sl, int col, long long ld) {
+    int sg = 0;
+    while (sg + 1 < sl.nseg && col >= sl.start[sg + 1]) ++sg;
+    return sl.p[sg] + (long long)(col - sl.start[sg]) * ld;
+}
+
+constexpr int GT = 64;          // output tile edge
+constexpr int GKC = 16;         // complex rows per LDS chunk (32 real rows)
+constexpr int GKR = 2 * GKC;
+constexpr int GPAD = GKR + 1;   // LDS row pitch in doubles (bank spread)
+
+__global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegList A, long long lda, SegList B,
+                                              long long ldb, long long kper, int tiles_n, int herm,
+                                              double2* __restrict__ part) {
+    __shared__ double la[GT * GPAD];
+    __shared__ double lb[GT * GPAD];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int tij = blockIdx.x;
+    const int ti = tij / tiles_n, tj = tij % tiles_n;
+    const int split = blockIdx.y;
+    double2* out = part + (long long)split * m1 * m2;
+    if (herm && ti > tj) return;
+    const int p0 = ti * GT, q0 = tj * GT;
+    const long long k0 = (long long)split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // wave sub-tile
+    d4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) { accr[a][b] = d4{0, 0, 0, 0}; acci[a][b] = d4{0, 0, 0, 0}; }
+    // loader mapping: 256 threads, 16 lanes per column chunk, 16 columns per pass, 4 passes
+    const int lk = t & 15, lc = t >> 4;
+    const double2* acol[4];
+    const double2* bcol[4];
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int col = lc + 16 * pass;
+        acol[pass] = (p0 + col < m1) ? seg_col(A, p0 + col, lda) : nullptr;
+        bcol[pass] = (q0 + col < m2) ? seg_col(B, q0 + col, ldb) : nullptr;
+    }
+    for (long long kc = k0; kc < k1; kc += GKC) {
+        __syncthreads();
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const int col = lc + 16 * pass;
+            const long long kk = kc + lk;
+            double2 va = {0, 0}, vb = {0, 0};
+            if (kk < k1) {
+                if (acol[pass]) va = acol[pass][kk];
+                if (bcol[pass]) vb = bcol[pass][kk];
+            }
+            la[col * GPAD + 2 * lk] = va.x;
+            la[col * GPAD + 2 * lk + 1] = va.y;
+            lb[col * GPAD + 2 * lk] = vb.x;
+            lb[col * GPAD + 2 * lk + 1] = vb.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GKR; ks += 4) {
+            const int kr = ks + (lane >> 4);        // real row of this lane
+            const int ci = lane & 15;
+            double av[2], bv[2], bpv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = la[(wr + 16 * a + ci) * GPAD + kr];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int row = (wc + 16 * b + ci) * GPAD;
+                bv[b] = lb[row + kr];
+                // b'[2k] = Im B[k], b'[2k+1] = -Re B[k]
+                bpv[b] = (kr & 1) ? -lb[row + kr - 1] : lb[row + kr + 1];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    accr[a][b] = mfma(av[a], bv[b], accr[a][b]);
+                    acci[a][b] = mfma(av[a], bpv[b], acci[a][b]);
+                }
+        }
+    }
+    // write the partial tile: register r of lane l holds D[4 r + l / 16][l % 16]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + wr + 16 * a + 4 * r + (lane >> 4);
+                const int q = q0 + wc + 16 * b + (lane & 15);
+                if (p < m1 && q < m2) {
+                    double2 v;
+                    v.x = accr[a][b][r];
+                    v.y = acci[a][b][r];
+                    out[(long long)q * m1 + p] = v;
+                }
+            }
+}
+
+// C = alpha * sum_s part[s] (fixed order); Hermitian: fill the lower triangle from the upper.
+__global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restrict__ part, double alpha,
+                              double2* __restrict__ C, int ldc, int herm) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)m1 * m2) return;
+    int p = (int)(idx % m1), q = (int)(idx / m1);
+    const bool mirror = herm && (p / GT) > (q / GT);
+    const int ps = mirror ? q : p, qs = mirror ? p : q;
+    double sx = 0, sy = 0;
+    for (int s = 0; s < nsplit; ++s) {
+        double2 v = part[(long long)s * m1 * m2 + (long long)qs * m1 + ps];
+        sx += v.x;
+        sy += v.y;
+    }
+    double2 o;
+    o.x = alpha * sx;
+    o.y = mirror ? -alpha * sy : alpha * sy;
+    C[(long long)q * ldc + p] = o;
+}
+
+// ----------------------------------------------------------------------------------------
+// Update: Y (K x nb) = S (K x m) Cm (m x nb) + beta Y.  Each wave: 32 rows x 16*CB columns.
+//   Re Y = Re S Re C - Im S Im C,  Im Y = Re S Im C + Im S Re C.
+// ----------------------------------------------------------------------------------------
+template <int CB>
+__global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long long lds, int m,
+                                                const double2* __restrict__ Cm, int ldcm, int nb, double beta,
+                                                double2* __restrict__ Y, long long ldy) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const long long r0 = ((long long)blockIdx.x * 4 + wave) * 32;
+    const int j0 = blockIdx.y * 16 * CB;
+    const int ri = lane & 15, kq = lane >> 4;
+    d4 accr[2][CB], acci[2][CB];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) { accr[a][b] = d4{0, 0, 0, 0}; acci[a][b] = d4{0, 0, 0, 0}; }
+    for (int l0 = 0; l0 < m; l0 += 4) {
+        const int l = l0 + kq;                 // column of S for this lane
+        double2 sv[2] = {{0, 0}, {0, 0}};
+        if (l < m) {
+            const double2* col = seg_col(segs, l, lds);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const long long row = r0 + 16 * a + ri;
+                if (row < K) sv[a] = col[row];
+            }
+        }
+        double cr[CB], ci[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int j = j0 + 16 * b + ri;
+            double2 cv = {0, 0};
+            if (l < m && j < nb) cv = Cm[(long long)j * ldcm + l];
+            cr[b] = cv.x;
+            ci[b] = cv.y;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[a][b] = mfma(sv[a].x, cr[b], accr[a][b]);
+                accr[a][b] = mfma(-sv[a].y, ci[b], accr[a][b]);
+                acci[a][b] = mfma(sv[a].x, ci[b], acci[a][b]);
+                acci[a][b] = mfma(sv[a].y, cr[b], acci[a][b]);
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int j = j0 + 16 * b + (lane & 15);
+            if (j >= nb) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = r0 + 16 * a + 4 * r + (lane >> 4);
+                if (row >= K) continue;
+                double2* dst = Y + (long long)j * ldy + row;
+                double2 v;
+                v.x = accr[a][b][r];
+                v.y = acci[a][b][r];
+                if (beta != 0.0) {
+                    double2 o = *dst;
+                    v.x += beta * o.x;
+                    v.y += beta * o.y;
+                }
+                *dst = v;
+            }
+        }
+}
+
+// ----------------------------------------------------------------------------------------
+// Small dense kernels (m <= 512), column-major complex FP64.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ double2 mkc(double x, double y) { double2 r; r.x = x; r.y = y; return r; }
+__device__ __forceinline__ double2 conjd(double2 a) { return mkc(a.x, -a.y); }
+
+__global__ void k_small_gemm(int tA, int tB, int m, int n, int k, double2 alpha, const double2* __restrict__ A,
+                             int lda, const double2* __restrict__ B, int ldb, double2 beta, double2* C, int ldc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= n) return;
+    double sx = 0, sy = 0;
+    for (int l = 0; l < k; ++l) {
+        double2 a = tA ? conjd(A[(long long)i * lda + l]) : A[(long long)l * lda + i];
+        double2 b = tB ? conjd(B[(long long)l * ldb + j]) : B[(long long)j * ldb + l];
+        sx += a.x * b.x - a.y * b.y;
+        sy += a.x * b.y + a.y * b.x;
+    }
+    double2 s = mkc(alpha.x * sx - alpha.y * sy, alpha.x * sy + alpha.y * sx);
+    double2* dst = C + (long long)j * ldc + i;
+    if (beta.x != 0.0 || beta.y != 0.0) {
+        double2 o = *dst;
+        s.x += beta.x * o.x - beta.y * o.y;
+        s.y += beta.x * o.y + beta.y * o.x;
+    }
+    *dst = s;
+}
+
+// Right-looking Cholesky A = L L^H in one workgroup; lower triangle kept, upper zeroed.
+__global__ void __launch_bounds__(1024) k_small_cholesky(int m, double2* A, int lda, int* info) {
+    __shared__ double piv;
+    __shared__ int bad;
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        if (t == 0) {
+            double d = A[(long long)j * lda + j].x;
+            if (!(d > 0.0) || !isfinite(d)) { bad = j + 1; piv = 1.0; }
+            else piv = sqrt(d);
+        }
+        __syncthreads();
+        if (bad) break;
+        const double inv = 1.0 / piv;
+        for (int i = j + t; i < m; i += nt) {
+            double2 v = A[(long long)j * lda + i];
+            A[(long long)j * lda + i] = (i == j) ? mkc(piv, 0.0) : mkc(v.x * inv, v.y * inv);
+        }
+        __syncthreads();
+        // trailing update: A[i][l] -= L[i][j] conj(L[l][j]) for j < l <= i
+        const int rem = m - j - 1;
+        const long long tot = (long long)rem * rem;
+        for (long long e = t; e < tot; e += nt) {
+            const int i = j + 1 + (int)(e % rem), l = j + 1 + (int)(e / rem);
+            if (l > i) continue;
+            double2 li = A[(long long)j * lda + i], ll = A[(long long)j * lda + l];
+            double2* d = A + (long long)l * lda + i;
+            double2 o = *d;
+            o.x -= li.x * ll.x + li.y * ll.y;
+            o.y -= li.y * ll.x - li.x * ll.y;
+            *d = o;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // zero the strict upper triangle
+    for (long long e = t; e < (long long)m * m; e += nt) {
+        const int i = (int)(e % m), l = (int)(e / m);
+        if (l > i) A[(long long)l * lda + i] = mkc(0.0, 0.0);
+    }
+    if (t == 0) *info = bad;
+}
+
+// One-sided Jacobi SVD (round-robin ordering, complex rotations) in one workgroup.
+// G (rows x m) -> G V; V (m x m) accumulates the rotations (starts as identity).
+__global__ void __launch_bounds__(1024) k_small_jacobi(int rows, int m, double2* G, int ldg, double2* V, int ldv,
+                                                      int tpp, int max_sweeps) {
+    __shared__ int rotated;
+    __shared__ double fro[32];
+    const int t = threadIdx.x;
+    const int mm = (m + 1) & ~1;           // even number of players (one padding column)
+    const int npairs = mm / 2;
+    const int pair = t / tpp, sub = t % tpp;
+    double fs = 0;
+    for (long long e = t; e < (long long)m * m; e += blockDim.x) {
+        const int i = (int)(e % m), l = (int)(e / m);
+        V[(long long)l * ldv + i] = mkc(i == l ? 1.0 : 0.0, 0.0);
+    }
+    for (long long e = t; e < (long long)rows * m; e += blockDim.x) {
+        const double2 g = G[(e / rows) * ldg + e % rows];
+        fs += g.x * g.x + g.y * g.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) fs += __shfl_down(fs, off);
+    if ((t & 63) == 0) fro[t >> 6] = fs;
+    __syncthreads();
+    double frob2 = 0;
+    for (int wv = 0; wv < (int)((blockDim.x + 63) / 64); ++wv) frob2 += fro[wv];
+    // columns below 1e-15 ||G||_F are numerically zero: no rotation against them
+    const double negl = 1e-30 * frob2;
+    const double tol = 1e-15;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (t == 0) rotated = 0;
+        __syncthreads();
+        for (int rnd = 0; rnd < mm - 1; ++rnd) {
+            int pcol = -1, qcol = -1;
+            if (pair < npairs) {
+                auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (mm - 1)) + 1; };
+                pcol = player(pair);
+                qcol = player(mm - 1 - pair);
+                if (pcol > qcol) { int tmp = pcol; pcol = qcol; qcol = tmp; }
+                if (qcol >= m) pcol = -1;      // padding player
+            }
+            double al = 0, be = 0, gx = 0, gy = 0;
+            if (pcol >= 0) {
+                const double2* gp = G + (long long)pcol * ldg;
+                const double2* gq = G + (long long)qcol * ldg;
+                for (int i = sub; i < rows; i += tpp) {
+                    double2 a = gp[i], b = gq[i];
+                    al += a.x * a.x + a.y * a.y;
+                    be += b.x * b.x + b.y * b.y;
+                    gx += a.x * b.x + a.y * b.y;     // conj(a) b
+                    gy += a.x * b.y - a.y * b.x;
+                }
+            }
+            for (int off = 1; off < tpp; off <<= 1) {
+                al += __shfl_xor(al, off);
+                be += __shfl_xor(be, off);
+                gx += __shfl_xor(gx, off);
+                gy += __shfl_xor(gy, off);
+            }
+            if (pcol >= 0) {
+                const double g = sqrt(gx * gx + gy * gy);
+                if (g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
+                    if (sub == 0) rotated = 1;
+                    const double zeta = (be - al) / (2.0 * g);
+                    const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
+                                                         : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                    // e^{-i theta} with gamma = |gamma| e^{i theta}
+                    const double ex = gx / g, ey = -gy / g;
+                    // [p', q'] = [c p - s e q, s p + c e q]
+                    double2* gp = G + (long long)pcol * ldg;
+                    double2* gq = G + (long long)qcol * ldg;
+                    for (int i = sub; i < rows; i += tpp) {
+                        double2 a = gp[i], b = gq[i];
+                        double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
+                        gp[i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                        gq[i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+                    }
+                    double2* vp = V + (long long)pcol * ldv;
+                    double2* vq = V + (long long)qcol * ldv;
+                    for (int i = sub; i < m; i += tpp) {
+                        double2 a = vp[i], b = vq[i];
+                        double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
+                        vp[i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                        vq[i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        if (!rotated) break;
+        __syncthreads();
+    }
+}
+
+// column norms of G (rows x m) into s; permutation to descending order (stable), applied to
+// G and V through the copies Gs, Vs.
+__global__ void __launch_bounds__(1024) k_small_sort(int rows, int m, double2* G, int ldg, double2* V, int ldv,
+                                                    double* s, double2* Gs, double2* Vs) {
+    __shared__ double nrm[512];
+    __shared__ int perm[512];
+    const int t = threadIdx.x;
+    for (int j = t; j < m; j += blockDim.x) {
+        double a = 0;
+        for (int i = 0; i < rows; ++i) {
+            double2 v = G[(long long)j * ldg + i];
+            a += v.x * v.x + v.y * v.y;
+        }
+        nrm[j] = sqrt(a);
+    }
+    __syncthreads();
+    for (int j = t; j < m; j += blockDim.x) {
+        int rank = 0;
+        for (int i = 0; i < m; ++i)
+            if (nrm[i] > nrm[j] || (nrm[i] == nrm[j] && i < j)) ++rank;
+        perm[rank] = j;
+    }
+    __syncthreads();
+    for (long long e = t; e < (long long)rows * m; e += blockDim.x) {
+        const int i = (int)(e % rows), l = (int)(e / rows);
+        Gs[e] = G[(long long)l * ldg + i];
+    }
+    for (long long e = t; e < (long long)m * m; e += blockDim.x) {
+        const int i = (int)(e % m), l = (int)(e / m);
+        Vs[e] = V[(long long)l * ldv + i];
+    }
+    __syncthreads();
+    for (long long e = t; e < (long long)rows * m; e += blockDim.x) {
+        const int i = (int)(e % rows), l = (int)(e / rows);
+        G[(long long)l * ldg + i] = Gs[(long long)perm[l] * rows + i];
+    }
+    for (long long e = t; e < (long long)m * m; e += blockDim.x) {
+        const int i = (int)(e % m), l = (int)(e / m);
+        V[(long long)l * ldv + i] = Vs[(long long)perm[l] * m + i];
+    }
+    for (int j = t; j < m; j += blockDim.x) s[j] = nrm[perm[j]];
+}
+
+// ----------------------------------------------------------------------------------------
+// Column reductions (two-stage, fixed order)
+// ----------------------------------------------------------------------------------------
+constexpr int RB = 256;
+__global__ void __launch_bounds__(RB) k_colnorm2_part(long long K, const double2* __restrict__ X, long long ldx,
+                                                      long long kper, double* __restrict__ part) {
+    __shared__ double red[RB / 64];
+    const int col = blockIdx.y, chunk = blockIdx.x;
+    const long long k0 = chunk * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const double2* x = X + (long long)col * ldx;
+    double s = 0;
+    for (long long k = k0 + threadIdx.x; k < k1; k += RB) {
+        double2 v = x[k];
+        s += v.x * v.x + v.y * v.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0;
+        for (int w = 0; w < RB / 64; ++w) a += red[w];
+        part[(long long)col * gridDim.x + chunk] = a;
+    }
+}
+
+__global__ void k_colnorm2_final(int ncols, int nchunk, const double* __restrict__ part, double* out) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncols) return;
+    double a = 0;
+    for (int c = 0; c < nchunk; ++c) a += part[(long long)col * nchunk + c];
+    out[col] = a;
+}
+
+}  // namespace
+
+// ======================================================================================
+// host wrappers
+// ======================================================================================
+static bool make_seglist(const Seg* segs, int nseg, SegList* sl, int* m) {
+    if (nseg < 1 || nseg > 4) return false;
+    *sl = SegList{};
+    int tot = 0;
+    for (int i = 0; i < nseg; ++i) {
+        sl->p[i] = (const double2*)segs[i].p;
+        sl->start[i] = tot;
+        tot += segs[i].ncols;
+    }
+    sl->start[nseg] = tot;
+    sl->nseg = nseg;
+    *m = tot;
+    return true;
+}
+
+bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long lda, const Seg* sb, int nbs,
+                    long long ldb, double alpha, double2* C, int ldc, int hermitian) {
+    SegList A, B;
+    int m1 = 0, m2 = 0;
+    if (!make_seglist(sa, na, &A, &m1) || !make_seglist(sb, nbs, &B, &m2))
+        return ctx_fail(c, BDG_EINVAL, "gram: 1..4 segments");
+    if (m1 <= 0 || m2 <= 0) return BDG_OK;
+    const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
+    const int ntiles = tm * tn;
+    long long nsplit = std::max<long long>(1, std::min<long long>((K + 511) / 512, 2048 / ntiles));
+    long long kper = (K + nsplit - 1) / nsplit;
+    kper = ((kper + GKC - 1) / GKC) * GKC;
+    nsplit = (K + kper - 1) / kper;
+    if (nsplit < 1) nsplit = 1;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
+    dim3 grid((unsigned)ntiles, (unsigned)nsplit);
+    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, c->stream, K, m1, m2, A, lda, B, ldb, kper, tn,
+                       hermitian ? 1 : 0, (double2*)ws);
+    BDG_HIP(c, hipGetLastError());
+    const long long tot = (long long)m1 * m2;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,
+                       (int)nsplit, (const double2*)ws, alpha, C, ldc, hermitian ? 1 : 0);
+    return hip_check(c, hipGetLastError(), "k_gram");
+}
+
+template <>
+bdg_status gram<double2, double2>(bdg_ctx* c, long long K, int m1, int m2, const double2* A, long long lda,
+                                  const double2* B, long long ldb, double alpha, double2* C, int ldc,
+                                  int hermitian) {
+    Seg a{A, m1}, b{B, m2};
+    return gram_seg(c, K, &a, 1, lda, &b, 1, ldb, alpha, C, ldc, hermitian);
+}
+
+bdg_status update(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cm, int ldcm,
+                  int nb, double beta, double2* Y, long long ldy) {
+    if (nb <= 0 || K <= 0) return BDG_OK;
+    SegList sl;
+    int m = 0;
+    if (!make_seglist(segs, nseg, &sl, &m)) return ctx_fail(c, BDG_EINVAL, "update: 1..4 segments");
+    const int cb = std::min(5, (nb + 15) / 16);
+    const int ctiles = (nb + 16 * cb - 1) / (16 * cb);
+    dim3 grid((unsigned)((K + 127) / 128), (unsigned)ctiles);
+    switch (cb) {
+        case 1: hipLaunchKernelGGL(k_update<1>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
+        case 2: hipLaunchKernelGGL(k_update<2>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
+        case 3: hipLaunchKernelGGL(k_update<3>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
+        case 4: hipLaunchKernelGGL(k_update<4>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
+        default: hipLaunchKernelGGL(k_update<5>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
+    }
+    return hip_check(c, hipGetLastError(), "k_update");
+}
+
+bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, double2 alpha, const double2* A,
+                      int lda, const double2* B, int ldb, double2 beta, double2* C, int ldc) {
+    if (m <= 0 || n <= 0) return BDG_OK;
+    dim3 grid((unsigned)((m + 127) / 128), (unsigned)n);
+    hipLaunchKernelGGL(k_small_gemm, grid, dim3(128), 0, c->stream, transA, transB, m, n, k, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+    return hip_check(c, hipGetLastError(), "k_small_gemm");
+}
+
+bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev) {
+    if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_cholesky: m > 512");
+    hipLaunchKernelGGL(k_small_cholesky, dim3(1), dim3(1024), 0, c->stream, m, A, lda, info_dev);
+    return hip_check(c, hipGetLastError(), "k_small_cholesky");
+}
+
+bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s) {
+    if (m <= 0) return BDG_OK;
+    if (m > 512 || rows > 4096) return ctx_fail(c, BDG_EINVAL, "small_svd: size out of range");
+    const int npairs = ((m + 1) & ~1) / 2;
+    int tpp = 64;
+    while (tpp > 1 && npairs * tpp > 1024) tpp >>= 1;
+    const int threads = ((npairs * tpp + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_small_jacobi, dim3(1), dim3(threads), 0, c->stream, rows, m, G, ldg, V, ldv, tpp, 60);
+    BDG_HIP(c, hipGetLastError());
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 1, ((size_t)rows * m + (size_t)m * m) * sizeof(double2), &ws));
+    hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, c->stream, rows, m, G, ldg, V, ldv, s, (double2*)ws,
+                       (double2*)ws + (size_t)rows * m);
+    return hip_check(c, hipGetLastError(), "k_small_sort");
+}
+
+bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx, double* out_dev) {
+    if (ncols <= 0) return BDG_OK;
+    int nchunk = (int)std::min<long long>(256, (K + 8191) / 8192);
+    if (nchunk < 1) nchunk = 1;
+    const long long kper = (K + nchunk - 1) / nchunk;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 2, (size_t)ncols * nchunk * sizeof(double), &ws));
+    hipLaunchKernelGGL(k_colnorm2_part, dim3((unsigned)nchunk, (unsigned)ncols), dim3(RB), 0, c->stream, K, X, ldx,
+                       kper, (double*)ws);
+    BDG_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((ncols + 127) / 128)), dim3(128), 0, c->stream, ncols,
+                       nchunk, (const double*)ws, out_dev);
+    return hip_check(c, hipGetLastError(), "k_colnorm2");
+}

@@ -1,0 +1,481 @@
+// Matrix-free BdG operator on gfx950: LDS-staged Stockham FFTs along each grid axis, the
+// kinetic multiplier |k|^2/2 (Section 3.1, eq. laplace_approx), and the pointwise 3x3
+// coupling of H_+ = A + B, H_- = A - B in physical space (eqs. def_bfA, def_bfB; the
+// matrix-vector product of Section 3.2).
+//
+// One pass over HBM per axis and direction; the last axis fuses forward FFT, multiplier
+// and inverse FFT in LDS/registers, and the final x pass fuses the inverse FFT with the
+// coupling:  3-D: x-fwd | y-fwd | z-fwd*k2*z-inv | y-inv | x-inv+couple,
+//            2-D: x-fwd | y-fwd*k2*y-inv | x-inv+couple,   1-D: one fused pass.
+// The output block Y doubles as the spectral workspace, so the operator needs no scratch.
+//
+// FFT engine: each thread owns four elements x[i + r N/4] (r = 0..3) of one line; radix-4
+// Stockham passes (and one radix-2 pass when log2 N is odd) exchange through LDS.  After
+// the last forward pass the thread again owns X[i + r N/4] in natural order, which is
+// exactly the input pattern of the inverse transform, so the fused multiplier costs no
+// extra exchange.  Twiddles exp(-2 pi i m/N) come from host-built float64 tables.
+#include "common.h"
+
+namespace {
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+template <typename V> struct FieldAddr {
+    V* lo;              // fields 0..2 of each vector (f or u half)
+    V* hi;              // fields 3..5 (g or v half)
+    long long vstride;  // distance between vectors
+    int fpv;            // fields per vector: 6 (both halves) or 3 (one half, at lo)
+    long long npts;
+    __device__ __forceinline__ V* field(long long f) const {
+        long long vec = f / fpv;
+        int c = (int)(f % fpv);
+        V* base = (c < 3) ? lo : hi;
+        return base + vec * vstride + (long long)(c % 3) * npts;
+    }
+};
+
+template <typename V, bool INV> __device__ __forceinline__ V mul_tw(V a, V w) {
+    return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+// 4-point DFT in registers (forward: W_4 = -i; inverse: +i), natural order output.
+template <typename V, bool INV> __device__ __forceinline__ void dft4(V v[4]) {
+    V t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    V t2 = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+    V t3 = INV ? cmk<V>(-d.y, d.x) : cmk<V>(d.y, -d.x);
+    v[0] = cadd(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[2] = csub(t0, t2);
+    v[3] = csub(t1, t3);
+}
+
+// In-line FFT of length N.  On entry v[r] = x[i + r N/4]; on exit v[r] = X[i + r N/4].
+// lds(e) = lds[lb + e * ls] is this line's exchange buffer.  Every thread of the block
+// must call it (barriers), including threads whose line is out of range.
+template <typename V, int N, bool INV>
+__device__ __forceinline__ void line_fft(V v[4], int i, V* __restrict__ lds, int lb, int ls,
+                                         const V* __restrict__ tw) {
+    constexpr int Q = N / 4;
+    constexpr int LG = ilog2c(N);
+    constexpr int NP4 = LG / 2;
+    constexpr bool R2 = (LG & 1) != 0;
+#pragma unroll
+    for (int s = 0; s < NP4; ++s) {
+        const int p = 1 << (2 * s);
+        const int k = i & (p - 1);
+        if (s > 0) {
+            const int step = N / (4 * p);
+#pragma unroll
+            for (int r = 1; r < 4; ++r) v[r] = mul_tw<V, INV>(v[r], tw[r * k * step]);
+        }
+        dft4<V, INV>(v);
+        const bool last = (s == NP4 - 1) && !R2;
+        if (!last) {
+            const int j = ((i - k) << 2) + k;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[lb + (j + r * p) * ls] = v[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = lds[lb + (i + r * Q) * ls];
+        }
+    }
+    if (R2) {
+        // final radix-2 pass (span N/2): butterflies i and i + N/4
+        v[2] = mul_tw<V, INV>(v[2], tw[i]);
+        v[3] = mul_tw<V, INV>(v[3], tw[i + Q]);
+        V a0 = cadd(v[0], v[2]), a2 = csub(v[0], v[2]);
+        V a1 = cadd(v[1], v[3]), a3 = csub(v[1], v[3]);
+        v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3;
+    }
+}
+
+struct MultSpec {
+    const double* s[3];   // |mu|^2/2 tables per axis (FFT order)
+    double scale;         // 1 / npts
+    double shift;         // preconditioner shift
+    int precond;          // 0: kinetic, 1: (k2 + shift)^-1
+};
+
+template <typename R>
+__device__ __forceinline__ R multiplier(const MultSpec& m, int mx, int my, int mz) {
+    double k2 = m.s[0][mx] + m.s[1][my] + m.s[2][mz];
+    double v = m.precond ? m.scale / (k2 + m.shift) : m.scale * k2;
+    return (R)v;
+}
+
+// ----------------------------------------------------------------------------------------
+// x pass: contiguous lines.  MODE 0: plain FFT (direction INV); MODE 1: fused forward,
+// multiplier, inverse (the x axis is the only axis: 1-D preconditioner / plain fused use).
+// ----------------------------------------------------------------------------------------
+template <typename V, int N, bool INV, int MODE>
+__global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<V> out,
+                                               long long nfields, long long lines_per_field,
+                                               const V* __restrict__ tw, MultSpec ms, int ny) {
+    using R = decltype(V::x);
+    constexpr int Q = N / 4;
+    constexpr int LPW = (1024 / N) > 0 ? (1024 / N) : 1;
+    __shared__ V lds[LPW * N];
+    const int t = threadIdx.x;
+    const int ln = t / Q, i = t % Q;
+    const long long gl = (long long)blockIdx.x * LPW + ln;
+    const bool valid = gl < nfields * lines_per_field;
+    const long long f = valid ? gl / lines_per_field : 0;
+    const long long l = valid ? gl % lines_per_field : 0;
+    const V* src = in.field(f) + l * N;
+    V* dst = out.field(f) + l * N;
+    V v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+    if (MODE == 0) {
+        line_fft<V, N, INV>(v, i, lds, ln * N, 1, tw);
+    } else {
+        line_fft<V, N, false>(v, i, lds, ln * N, 1, tw);
+        const int my = (int)(l % ny), mz = (int)(l / ny);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], multiplier<R>(ms, i + r * Q, my, mz));
+        line_fft<V, N, true>(v, i, lds, ln * N, 1, tw);
+    }
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[i + r * Q] = v[r];
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// Strided pass along axis y (axis=1) or z (axis=2), tiles of TX adjacent x columns.
+// MODE 0: plain FFT; MODE 1: fused forward * multiplier * inverse (last axis).
+// ----------------------------------------------------------------------------------------
+template <typename V, int N> struct StridedCfg {
+    static constexpr int TXA = 2048 / N;
+    static constexpr int TX = TXA < 16 ? (TXA < 1 ? 1 : TXA) : 16;
+    static constexpr int THREADS = TX * (N / 4);
+};
+
+template <typename V, int N, bool INV, int MODE>
+__global__ void __launch_bounds__(512) k_strided(FieldAddr<V> io, long long nfields, int nx, int ny,
+                                                 int axis, int tx, const V* __restrict__ tw, MultSpec ms) {
+    using R = decltype(V::x);
+    constexpr int Q = N / 4;
+    constexpr int TXM = StridedCfg<V, N>::TX;
+    __shared__ V lds[TXM * N];
+    const int t = threadIdx.x;               // blockDim.x == tx * N/4 (tx <= TXM)
+    const int c = t % tx, i = t / tx;
+    const int tiles = nx / tx;
+    // block -> (field, outer, tile)
+    const long long b = blockIdx.x;
+    const int tile = (int)(b % tiles);
+    const long long rest = b / tiles;
+    const int outer_n = (axis == 1) ? (int)(io.npts / ((long long)nx * ny)) : ny;   // z planes or y rows
+    const int outer = (int)(rest % outer_n);
+    const long long f = rest / outer_n;
+    const long long stride = (axis == 1) ? nx : (long long)nx * ny;
+    const long long outer_stride = (axis == 1) ? (long long)nx * ny : nx;
+    V* base = io.field(f) + outer * outer_stride + tile * tx + c;
+    V v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = base[(i + r * Q) * stride];
+    if (MODE == 0) {
+        line_fft<V, N, INV>(v, i, lds, c, tx, tw);
+    } else {
+        line_fft<V, N, false>(v, i, lds, c, tx, tw);
+        const int mx = tile * tx + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = i + r * Q;
+            const R m = (axis == 2) ? multiplier<R>(ms, mx, outer, e) : multiplier<R>(ms, mx, e, 0);
+            v[r] = cscale(v[r], m);
+        }
+        line_fft<V, N, true>(v, i, lds, c, tx, tw);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) base[(i + r * Q) * stride] = v[r];
+}
+
+// ----------------------------------------------------------------------------------------
+// Final x pass: inverse FFT of the six kinetic fields of QL lines of one vector, then the
+// pointwise coupling with the input fields.  FULL: the lines are loaded from X and
+// transformed forward, multiplied and inverted here (1-D grids).
+// FORM 1 (f, g):  y_f = T g + H_- g,  y_g = T f + H_+ f   (transpose swaps H_+ and H_-)
+// FORM 0 (u, v):  y_u = T u + A u + B v,  y_v = -(T v + B u + A v)  with A = (H_+ + H_-)/2,
+//                 B = (H_+ - H_-)/2 (transpose flips the sign of the B terms)
+// ----------------------------------------------------------------------------------------
+template <int N> struct CoupleCfg {
+    static constexpr int QL = (256 / N) > 0 ? (256 / N) : 1;
+    static constexpr int THREADS = 6 * QL * (N / 4);
+};
+
+template <typename V, int N, int FORM, int TRANS, bool FULL>
+__global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAddr<V> yout,
+                                                 long long lines_per_field, long long nlinegroups,
+                                                 const V* __restrict__ tw, MultSpec ms, int ny,
+                                                 const decltype(V::x)* __restrict__ coef) {
+    using R = decltype(V::x);
+    constexpr int Q = N / 4;
+    constexpr int QL = CoupleCfg<N>::QL;
+    __shared__ V lds[6 * QL * N];
+    const int t = threadIdx.x;
+    const int fld = t / (QL * Q);
+    const int q = (t / Q) % QL;
+    const int i = t % Q;
+    const long long b = blockIdx.x;
+    const long long vec = b / nlinegroups;
+    const long long l0 = (b % nlinegroups) * QL;
+    const long long l = l0 + q;
+    const bool valid = l < lines_per_field;
+    const long long npts = xin.npts;
+    V v[4];
+    if (FULL) {
+        const V* src = xin.field(vec * 6 + fld) + l * N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+        line_fft<V, N, false>(v, i, lds, (fld * QL + q) * N, 1, tw);
+        const int my = (int)(l % ny), mz = (int)(l / ny);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], multiplier<R>(ms, i + r * Q, my, mz));
+    } else {
+        const V* src = yout.field(vec * 6 + fld) + l * N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+    }
+    line_fft<V, N, true>(v, i, lds, (fld * QL + q) * N, 1, tw);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lds[(fld * QL + q) * N + i + r * Q] = v[r];
+    __syncthreads();
+    // coupling: one grid point per thread iteration
+    const V* x0 = xin.field(vec * 6 + 0);
+    const V* x3 = xin.field(vec * 6 + 3);
+    V* y0 = yout.field(vec * 6 + 0);
+    V* y3 = yout.field(vec * 6 + 3);
+    for (int pt = t; pt < QL * N; pt += blockDim.x) {
+        const int qq = pt / N, e = pt % N;
+        const long long ll = l0 + qq;
+        if (ll >= lines_per_field) continue;
+        const long long p = ll * N + e;
+        V xa[3], xb[3], ta[3], tb[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            xa[cc] = x0[cc * npts + p];
+            xb[cc] = x3[cc * npts + p];
+            ta[cc] = lds[(cc * QL + qq) * N + e];
+            tb[cc] = lds[((cc + 3) * QL + qq) * N + e];
+        }
+        R P[6], M[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            P[s] = coef[s * npts + p];
+            M[s] = coef[(6 + s) * npts + p];
+        }
+        // symmetric 3x3 from 6 entries (00, 01, 02, 11, 12, 22)
+        auto sym = [](const R* S, int a, int c2) -> R {
+            const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
+            const int idx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+            return S[idx];
+        };
+        V ya[3], yb[3];
+        if (FORM == 1) {
+            const R* Pa = TRANS ? M : P;   // operator acting on f (output half 1)
+            const R* Pb = TRANS ? P : M;   // operator acting on g (output half 0)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                V s0 = tb[a], s1 = ta[a];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    const R mb = sym(Pb, a, cc), ma = sym(Pa, a, cc);
+                    s0 = cmk<V>(s0.x + mb * xb[cc].x, s0.y + mb * xb[cc].y);
+                    s1 = cmk<V>(s1.x + ma * xa[cc].x, s1.y + ma * xa[cc].y);
+                }
+                ya[a] = s0;
+                yb[a] = s1;
+            }
+        } else {
+            const R sB = TRANS ? (R)-1 : (R)1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                V su = ta[a], sv = tb[a];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    const R pa = sym(P, a, cc), mm = sym(M, a, cc);
+                    const R A_ = (R)0.5 * (pa + mm), B_ = (R)0.5 * (pa - mm) * sB;
+                    su = cmk<V>(su.x + A_ * xa[cc].x + B_ * xb[cc].x, su.y + A_ * xa[cc].y + B_ * xb[cc].y);
+                    sv = cmk<V>(sv.x + B_ * xa[cc].x + A_ * xb[cc].x, sv.y + B_ * xa[cc].y + A_ * xb[cc].y);
+                }
+                ya[a] = su;
+                yb[a] = cmk<V>(-sv.x, -sv.y);
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            y0[cc * npts + p] = ya[cc];
+            y3[cc * npts + p] = yb[cc];
+        }
+    }
+}
+
+template <typename V> FieldAddr<V> fa_block(V* lo, V* hi, long long vstride, long long npts) {
+    FieldAddr<V> a; a.lo = lo; a.hi = hi; a.vstride = vstride; a.fpv = 6; a.npts = npts; return a;
+}
+template <typename V> FieldAddr<V> fa_fields(V* base, int fpv, long long vstride, long long npts) {
+    FieldAddr<V> a; a.lo = base; a.hi = base + 3 * npts; a.vstride = vstride; a.fpv = fpv; a.npts = npts; return a;
+}
+
+template <typename R> const typename cplx_of<R>::type* tw_of(bdg_ctx* c, int axis);
+template <> const double2* tw_of<double>(bdg_ctx* c, int axis) { return c->tw64[axis]; }
+template <> const float2* tw_of<float>(bdg_ctx* c, int axis) { return c->tw32[axis]; }
+template <typename R> const R* coef_of(bdg_ctx* c);
+template <> const double* coef_of<double>(bdg_ctx* c) { return c->coef64; }
+template <> const float* coef_of<float>(bdg_ctx* c) { return c->coef32; }
+
+MultSpec make_ms(bdg_ctx* c, int precond, double shift) {
+    MultSpec m;
+    for (int a = 0; a < 3; ++a) m.s[a] = c->sym64[a];
+    m.scale = 1.0 / (double)c->npts;
+    m.shift = shift;
+    m.precond = precond;
+    return m;
+}
+
+// --------------------------- dispatch over N ---------------------------------------------
+#define BDG_DISPATCH_N(NVAL, ...)                                        \
+    switch (NVAL) {                                                      \
+        case 8: { constexpr int NN = 8; __VA_ARGS__; } break;            \
+        case 16: { constexpr int NN = 16; __VA_ARGS__; } break;          \
+        case 32: { constexpr int NN = 32; __VA_ARGS__; } break;          \
+        case 64: { constexpr int NN = 64; __VA_ARGS__; } break;          \
+        case 128: { constexpr int NN = 128; __VA_ARGS__; } break;        \
+        case 256: { constexpr int NN = 256; __VA_ARGS__; } break;        \
+        case 512: { constexpr int NN = 512; __VA_ARGS__; } break;        \
+        default: return ctx_fail(c, BDG_EINVAL, "unsupported axis length"); \
+    }
+
+template <typename V, bool INV, int MODE>
+bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<V> out, long long nfields, MultSpec ms) {
+    const int N = c->n[0];
+    const long long lpf = c->npts / N;
+    BDG_DISPATCH_N(N, {
+        constexpr int LPW = (1024 / NN) > 0 ? (1024 / NN) : 1;
+        const long long nl = nfields * lpf;
+        dim3 grid((unsigned)((nl + LPW - 1) / LPW));
+        hipLaunchKernelGGL((k_xpass<V, NN, INV, MODE>), grid, dim3(LPW * (NN / 4)), 0, c->stream,
+                           in, out, nfields, lpf, (const V*)tw_of<decltype(V::x)>(c, 0), ms, c->n[1]);
+    });
+    return hip_check(c, hipGetLastError(), "k_xpass");
+}
+
+template <typename V, bool INV, int MODE>
+bdg_status run_strided(bdg_ctx* c, FieldAddr<V> io, long long nfields, int axis, MultSpec ms) {
+    const int N = c->n[axis];
+    const int nx = c->n[0], ny = c->n[1];
+    BDG_DISPATCH_N(N, {
+        constexpr int TXM = StridedCfg<V, NN>::TX;
+        const int tx = nx < TXM ? nx : TXM;
+        const long long outer = (axis == 1) ? (long long)c->n[2] : (long long)ny;
+        dim3 grid((unsigned)(nfields * outer * (nx / tx)));
+        hipLaunchKernelGGL((k_strided<V, NN, INV, MODE>), grid, dim3(tx * (NN / 4)), 0, c->stream,
+                           io, nfields, nx, ny, axis, tx, (const V*)tw_of<decltype(V::x)>(c, axis), ms);
+    });
+    return hip_check(c, hipGetLastError(), "k_strided");
+}
+
+template <typename V, int FORM, int TRANS, bool FULL>
+bdg_status run_couple(bdg_ctx* c, FieldAddr<const V> xin, FieldAddr<V> yout, long long nvec, MultSpec ms) {
+    using R = decltype(V::x);
+    const int N = c->n[0];
+    const long long lpf = c->npts / N;
+    BDG_DISPATCH_N(N, {
+        constexpr int QL = CoupleCfg<NN>::QL;
+        const long long ngroups = (lpf + QL - 1) / QL;
+        dim3 grid((unsigned)(nvec * ngroups));
+        hipLaunchKernelGGL((k_couple<V, NN, FORM, TRANS, FULL>), grid, dim3(CoupleCfg<NN>::THREADS), 0,
+                           c->stream, xin, yout, lpf, ngroups, (const V*)tw_of<R>(c, 0), ms, c->n[1],
+                           coef_of<R>(c));
+    });
+    return hip_check(c, hipGetLastError(), "k_couple");
+}
+
+template <typename V, int FORM, int TRANS>
+bdg_status apply_impl(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y) {
+    MultSpec ms = make_ms(c, 0, 0.0);
+    const long long nf = 6LL * nvec;
+    if (c->dim == 1) return run_couple<V, FORM, TRANS, true>(c, X, Y, nvec, ms);
+    BDG_TRY((run_xpass<V, false, 0>(c, X, Y, nf, ms)));
+    if (c->dim == 2) {
+        BDG_TRY((run_strided<V, false, 1>(c, Y, nf, 1, ms)));
+    } else {
+        BDG_TRY((run_strided<V, false, 0>(c, Y, nf, 1, ms)));
+        BDG_TRY((run_strided<V, false, 1>(c, Y, nf, 2, ms)));
+        BDG_TRY((run_strided<V, true, 0>(c, Y, nf, 1, ms)));
+    }
+    return run_couple<V, FORM, TRANS, false>(c, X, Y, nvec, ms);
+}
+
+}  // namespace
+
+template <typename R>
+bdg_status launch_apply(bdg_ctx* c, int form, int transpose, int nvec,
+                        BlockRef<const typename cplx_of<R>::type> X, BlockRef<typename cplx_of<R>::type> Y) {
+    using V = typename cplx_of<R>::type;
+    if (nvec <= 0) return BDG_OK;
+    FieldAddr<const V> xa = fa_block<const V>(X.lo, X.hi, X.vstride, c->npts);
+    FieldAddr<V> ya = fa_block<V>(Y.lo, Y.hi, Y.vstride, c->npts);
+    if (form == BDG_FORM_FG) {
+        return transpose ? apply_impl<V, 1, 1>(c, nvec, xa, ya) : apply_impl<V, 1, 0>(c, nvec, xa, ya);
+    }
+    return transpose ? apply_impl<V, 0, 1>(c, nvec, xa, ya) : apply_impl<V, 0, 0>(c, nvec, xa, ya);
+}
+
+template <typename R>
+bdg_status launch_fourier(bdg_ctx* c, int nfields, int fpv, long long vstride,
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, int precond, double shift) {
+    using V = typename cplx_of<R>::type;
+    if (nfields <= 0) return BDG_OK;
+    MultSpec ms = make_ms(c, precond, shift);
+    FieldAddr<const V> xa = fa_fields<const V>(X, fpv, vstride, c->npts);
+    FieldAddr<V> ya = fa_fields<V>(Y, fpv, vstride, c->npts);
+    if (c->dim == 1) return run_xpass<V, false, 1>(c, xa, ya, nfields, ms);
+    BDG_TRY((run_xpass<V, false, 0>(c, xa, ya, nfields, ms)));
+    if (c->dim == 2) {
+        BDG_TRY((run_strided<V, false, 1>(c, ya, nfields, 1, ms)));
+    } else {
+        BDG_TRY((run_strided<V, false, 0>(c, ya, nfields, 1, ms)));
+        BDG_TRY((run_strided<V, false, 1>(c, ya, nfields, 2, ms)));
+        BDG_TRY((run_strided<V, true, 0>(c, ya, nfields, 1, ms)));
+    }
+    FieldAddr<const V> yc = fa_fields<const V>(Y, fpv, vstride, c->npts);
+    return run_xpass<V, true, 0>(c, yc, ya, nfields, ms);
+}
+
+template <typename R>
+bdg_status launch_fft(bdg_ctx* c, int nfields, const typename cplx_of<R>::type* X,
+                      typename cplx_of<R>::type* Y, int inverse) {
+    using V = typename cplx_of<R>::type;
+    if (nfields <= 0) return BDG_OK;
+    MultSpec ms = make_ms(c, 0, 0.0);
+    const long long vs = c->npts;
+    FieldAddr<const V> xa = fa_fields<const V>(X, 1, vs, c->npts);
+    FieldAddr<V> ya = fa_fields<V>(Y, 1, vs, c->npts);
+    if (inverse) {
+        BDG_TRY((run_xpass<V, true, 0>(c, xa, ya, nfields, ms)));
+        for (int a = 1; a < c->dim; ++a) BDG_TRY((run_strided<V, true, 0>(c, ya, nfields, a, ms)));
+    } else {
+        BDG_TRY((run_xpass<V, false, 0>(c, xa, ya, nfields, ms)));
+        for (int a = 1; a < c->dim; ++a) BDG_TRY((run_strided<V, false, 0>(c, ya, nfields, a, ms)));
+    }
+    return BDG_OK;
+}
+
+template bdg_status launch_apply<double>(bdg_ctx*, int, int, int, BlockRef<const double2>, BlockRef<double2>);
+template bdg_status launch_apply<float>(bdg_ctx*, int, int, int, BlockRef<const float2>, BlockRef<float2>);
+template <typename R>
+bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, double shift) {
+    return launch_fourier<R>(c, nfields, fpv, vstride, X, Y, 1, shift);
+}
+
+template bdg_status launch_fourier<double>(bdg_ctx*, int, int, long long, const double2*, double2*, int, double);
+template bdg_status launch_fourier<float>(bdg_ctx*, int, int, long long, const float2*, float2*, int, double);
+template bdg_status launch_precond<double>(bdg_ctx*, int, int, long long, const double2*, double2*, double);
+template bdg_status launch_precond<float>(bdg_ctx*, int, int, long long, const float2*, float2*, double);
+template bdg_status launch_fft<double>(bdg_ctx*, int, const double2*, double2*, int);
+template bdg_status launch_fft<float>(bdg_ctx*, int, const float2*, float2*, int);

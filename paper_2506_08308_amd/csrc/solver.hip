@@ -1,0 +1,987 @@
+// Structure-preserving block subspace iteration for the linear-response form of the BdG
+// problem (Section 3.2):  [[0, H_-], [H_+, 0]] [f; g] = omega [f; g].
+//
+// The paper solves it with its bi-orthogonal structure-preserving (BOSP) iteration and
+// names its ingredients (bi-orthogonal Gram-Schmidt, use of the generalized nullspace of
+// Section 2.3, LAPACK for the projected problem) without printing its steps.  This
+// implementation is a locally optimal block iteration of the Bai-Li family:
+//   basis      S_f = [F, W_f, P_f], S_g = [G, W_g, P_g] and their images H_+ S_f, H_- S_g;
+//   residual   R = H_+ F - G diag(w) (f-direction), H_- G - F diag(w) (g-direction);
+//   correction W = (|k|^2/2 + sigma)^-1 R, projected off the generalized nullspace
+//              (f orthogonal to ns(H_-), g orthogonal to ns(H_+) + Jordan partners);
+//   projection each basis is made orthonormal on its own (rank-revealing), the pairing
+//              matrix of the two orthonormal bases is bi-orthogonalized by an SVD
+//              (B = U Sigma V^H, C_f = R_f V Sigma^-1/2, C_g = R_g U Sigma^-1/2), and the
+//              projected problem K b = w a, M a = w b (M = C_f^H S_f^H H_+ S_f C_f,
+//              K = C_g^H S_g^H H_- S_g C_g) is solved through the Cholesky factors
+//              M = L_M L_M^H, K = L_K L_K^H and the SVD L_K^H L_M = U_G diag(w) V_G^H:
+//              a = L_K u, b = L_M v;
+//   update     F <- S_f a, G <- S_g b (and images), P from the W and P rows.
+// Gram matrices and updates run on the FP64 matrix cores; the projected problems on the
+// device in FP64; the host only reads back residual norms and small singular values.
+#include "common.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace {
+
+// BDG_DEBUG=1 prints per-iteration diagnostics of the subspace iteration to stderr
+bool debug_on() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("BDG_DEBUG");
+        v = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+__global__ void k_cols_axmy(long long K, int ncols, const double2* __restrict__ X, long long ldx,
+                            const double2* __restrict__ Y, long long ldy, const double* __restrict__ w,
+                            double2* __restrict__ Z, long long ldz) {
+    const int j = blockIdx.y;
+    const double s = w[j];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        double2 a = X[j * ldx + i], b = Y[j * ldy + i];
+        Z[j * ldz + i] = cmk<double2>(a.x - s * b.x, a.y - s * b.y);
+    }
+}
+
+__global__ void k_cols_scale(long long K, int ncols, double2* __restrict__ X, long long ldx, const double* __restrict__ s,
+                             int inv_sqrt) {
+    const int j = blockIdx.y;
+    double f = s[j];
+    if (inv_sqrt) f = f > 0 ? 1.0 / sqrt(f) : 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        double2 a = X[j * ldx + i];
+        X[j * ldx + i] = cmk<double2>(a.x * f, a.y * f);
+    }
+}
+
+__global__ void k_to32(long long K, int ncols, const double2* __restrict__ X, long long ldx, float2* __restrict__ Y,
+                       long long ldy) {
+    const int j = blockIdx.y;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        double2 a = X[j * ldx + i];
+        Y[j * ldy + i] = cmk<float2>((float)a.x, (float)a.y);
+    }
+}
+
+__global__ void k_to64(long long K, int ncols, const float2* __restrict__ X, long long ldx, double2* __restrict__ Y,
+                       long long ldy) {
+    const int j = blockIdx.y;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        float2 a = X[j * ldx + i];
+        Y[j * ldy + i] = cmk<double2>((double)a.x, (double)a.y);
+    }
+}
+
+// Y += alpha X (complex alpha), single column
+__global__ void k_axpy(long long K, double2 alpha, const double2* __restrict__ X, double2* __restrict__ Y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        double2 x = X[i], y = Y[i];
+        Y[i] = cmk<double2>(y.x + alpha.x * x.x - alpha.y * x.y, y.y + alpha.x * x.y + alpha.y * x.x);
+    }
+}
+
+// P = Z + beta P
+__global__ void k_xpby(long long K, const double2* __restrict__ Z, double2 beta, double2* __restrict__ P) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        double2 z = Z[i], p = P[i];
+        P[i] = cmk<double2>(z.x + beta.x * p.x - beta.y * p.y, z.y + beta.x * p.y + beta.y * p.x);
+    }
+}
+
+// generators of the nullspaces (Section 2.3): Phi, S_z Phi, S_x Phi, K Phi (K = -i S_y), complex
+__global__ void k_candidates(long long npts, const double* __restrict__ phi, double2* __restrict__ out) {
+    const double r2 = 0.70710678118654752440;
+    const long long nh = 3 * npts;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x) {
+        const double a = phi[p], b = phi[npts + p], d = phi[2 * npts + p];
+        const double v[4][3] = {{a, b, d}, {a, 0.0, -d}, {r2 * b, r2 * (a + d), r2 * b}, {-r2 * b, r2 * (a - d), r2 * b}};
+        for (int c = 0; c < 4; ++c)
+            for (int s = 0; s < 3; ++s) out[c * nh + s * npts + p] = cmk<double2>(v[c][s], 0.0);
+    }
+}
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
+// complex standard normal (re + i im)/sqrt2 from a counter-based generator (Box-Muller)
+__global__ void k_randn(long long n, unsigned long long seed, double2* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        unsigned long long a = splitmix64(seed * 0x632BE59BD9B4E019ULL + 2 * (unsigned long long)i);
+        unsigned long long b = splitmix64(seed * 0x632BE59BD9B4E019ULL + 2 * (unsigned long long)i + 1);
+        const double u1 = ((a >> 11) + 1) * (1.0 / 9007199254740993.0);
+        const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);
+        const double r = sqrt(-2.0 * log(u1));
+        double s, co;
+        sincos(2.0 * M_PI * u2, &s, &co);
+        out[i] = cmk<double2>(r * co * 0.70710678118654752440, r * s * 0.70710678118654752440);
+    }
+}
+
+// small matrices: A(:, j) *= s_j^pw (s_j <= 0 -> 0)
+__global__ void k_small_colpow(int rows, int cols, double2* A, int lda, const double* __restrict__ s, double pw) {
+    const int j = blockIdx.x;
+    if (j >= cols) return;
+    const double sj = s[j];
+    const double f = sj > 0 ? pow(sj, pw) : 0.0;
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+        double2 a = A[(long long)j * lda + i];
+        A[(long long)j * lda + i] = cmk<double2>(a.x * f, a.y * f);
+    }
+}
+
+// out(:, t) = A(:, idx[t]) * scale[t]
+__global__ void k_small_gather(int rows, int nsel, const double2* __restrict__ A, int lda, const int* __restrict__ idx,
+                               const double* __restrict__ scale, double2* __restrict__ out, int ldo) {
+    const int t = blockIdx.x;
+    if (t >= nsel) return;
+    const int j = idx[t];
+    const double f = scale[t];
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+        double2 a = A[(long long)j * lda + i];
+        out[(long long)t * ldo + i] = cmk<double2>(a.x * f, a.y * f);
+    }
+}
+
+// dinv_i = 1/sqrt(A_ii), A_ij *= dinv_i dinv_j (symmetric diagonal scaling).  Columns whose
+// squared norm is below 1e-20 of the largest count as zero (dinv_i = 0), so that the rank
+// detection that follows still sees them as dependent.
+__global__ void k_small_diagscale(int m, double2* A, int lda, double* __restrict__ dinv) {
+    __shared__ double ds[512];
+    __shared__ double dmax;
+    if (threadIdx.x == 0) {
+        double mx = 0;
+        for (int i = 0; i < m; ++i) mx = fmax(mx, A[(long long)i * lda + i].x);
+        dmax = mx;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double d = A[(long long)i * lda + i].x;
+        ds[i] = (d > 1e-20 * dmax && d > 0) ? 1.0 / sqrt(d) : 0.0;
+        dinv[i] = ds[i];
+    }
+    __syncthreads();
+    for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        double2 a = A[(long long)j * lda + i];
+        const double f = ds[i] * ds[j];
+        A[(long long)j * lda + i] = cmk<double2>(a.x * f, a.y * f);
+    }
+}
+
+// A(i, :) *= d_i
+__global__ void k_small_rowscale(int rows, int cols, double2* A, int lda, const double* __restrict__ d) {
+    const int j = blockIdx.x;
+    if (j >= cols) return;
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+        double2 a = A[(long long)j * lda + i];
+        A[(long long)j * lda + i] = cmk<double2>(a.x * d[i], a.y * d[i]);
+    }
+}
+
+__global__ void k_small_herm(int m, double2* A, int lda) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= m || j >= m || i > j) return;
+    double2 a = A[(long long)j * lda + i], b = A[(long long)i * lda + j];
+    const double2 h = cmk<double2>(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    A[(long long)j * lda + i] = h;
+    A[(long long)i * lda + j] = cmk<double2>(h.x, -h.y);
+}
+
+__global__ void k_small_copy(int rows, int cols, const double2* __restrict__ A, int lda, double2* __restrict__ B, int ldb) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x)
+        B[(long long)j * ldb + i] = A[(long long)j * lda + i];
+}
+
+// u = f + g, v = f - g for ncols columns (half columns of stride nh) into interleaved vectors
+__global__ void k_make_uv(long long nh, int ncols, const double2* __restrict__ F, const double2* __restrict__ G,
+                          const double* __restrict__ scale, double2* __restrict__ UV) {
+    const int j = blockIdx.y;
+    const double s = scale[j];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (long long)gridDim.x * blockDim.x) {
+        double2 f = F[j * nh + i], g = G[j * nh + i];
+        UV[j * 2 * nh + i] = cmk<double2>(s * (f.x + g.x), s * (f.y + g.y));
+        UV[j * 2 * nh + nh + i] = cmk<double2>(s * (f.x - g.x), s * (f.y - g.y));
+    }
+}
+
+dim3 grid_cols(long long K, int ncols) {
+    long long bx = (K + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    return dim3((unsigned)bx, (unsigned)ncols);
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side helpers
+// ---------------------------------------------------------------------------------------
+struct Small {
+    int cap = 0;                 // max dimension
+    double2* buf[14] = {};
+    double* s[4] = {};
+    int* info = nullptr;
+    int* idx = nullptr;
+    double* dscale = nullptr;
+};
+
+bdg_status small_alloc(bdg_ctx* c, Small& w, int cap) {
+    w.cap = cap;
+    for (int i = 0; i < 14; ++i) BDG_TRY(ctx_alloc(c, (void**)&w.buf[i], (size_t)cap * cap * sizeof(double2)));
+    for (int i = 0; i < 4; ++i) BDG_TRY(ctx_alloc(c, (void**)&w.s[i], (size_t)cap * sizeof(double)));
+    BDG_TRY(ctx_alloc(c, (void**)&w.info, 4 * sizeof(int)));
+    BDG_TRY(ctx_alloc(c, (void**)&w.idx, (size_t)cap * sizeof(int)));
+    BDG_TRY(ctx_alloc(c, (void**)&w.dscale, 2 * (size_t)cap * sizeof(double)));
+    return BDG_OK;
+}
+void small_free(bdg_ctx* c, Small& w) {
+    for (int i = 0; i < 14; ++i) ctx_free(c, w.buf[i]);
+    for (int i = 0; i < 4; ++i) ctx_free(c, w.s[i]);
+    ctx_free(c, w.info);
+    ctx_free(c, w.idx);
+    ctx_free(c, w.dscale);
+    w = Small{};
+}
+
+const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0};
+
+bdg_status d2h(bdg_ctx* c, void* dst, const void* src, size_t bytes) {
+    BDG_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+bdg_status h2d(bdg_ctx* c, void* dst, const void* src, size_t bytes) {
+    BDG_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+
+bdg_status small_copy(bdg_ctx* c, int rows, int cols, const double2* A, int lda, double2* B, int ldb) {
+    if (rows <= 0 || cols <= 0) return BDG_OK;
+    hipLaunchKernelGGL(k_small_copy, dim3((unsigned)((rows + 255) / 256), (unsigned)cols), dim3(256), 0, c->stream,
+                       rows, cols, A, lda, B, ldb);
+    return hip_check(c, hipGetLastError(), "k_small_copy");
+}
+
+bdg_status small_colpow(bdg_ctx* c, int rows, int cols, double2* A, int lda, const double* s, double pw) {
+    if (rows <= 0 || cols <= 0) return BDG_OK;
+    hipLaunchKernelGGL(k_small_colpow, dim3((unsigned)cols), dim3(256), 0, c->stream, rows, cols, A, lda, s, pw);
+    return hip_check(c, hipGetLastError(), "k_small_colpow");
+}
+
+// R (m x r) with S R orthonormal, from the Hermitian PSD Gram matrix Gm (m x m): the
+// Gram matrix is first scaled to unit diagonal (columns of very different norms would
+// otherwise hide small independent components), then G~ = V diag(l) V^H (Jacobi) and
+// R = D^-1/2 V diag(l)^-1/2 over the eigenvalues l > rtol * max(l).
+bdg_status orth_factor(bdg_ctx* c, Small& w, int m, const double2* Gm, double2* T, double2* R, double* s, double rtol,
+                       int* r_out) {
+    BDG_TRY(small_copy(c, m, m, Gm, m, T, m));
+    double* dinv = w.dscale + w.cap;          // second half of the scale buffer
+    hipLaunchKernelGGL(k_small_diagscale, dim3(1), dim3(1024), 0, c->stream, m, T, m, dinv);
+    BDG_HIP(c, hipGetLastError());
+    BDG_TRY(small_svd(c, m, m, T, m, R, m, s));
+    std::vector<double> hs(m);
+    BDG_TRY(d2h(c, hs.data(), s, m * sizeof(double)));
+    int r = 0;
+    while (r < m && hs[r] > rtol * hs[0] && hs[r] > 0) ++r;
+    BDG_TRY(small_colpow(c, m, r, R, m, s, -0.5));
+    hipLaunchKernelGGL(k_small_rowscale, dim3((unsigned)r), dim3(256), 0, c->stream, m, r, R, m, (const double*)dinv);
+    BDG_HIP(c, hipGetLastError());
+    *r_out = r;
+    return BDG_OK;
+}
+
+// Projected problem (see file header).  Inputs m x m (ld m): Gf, Gg, Br, Mr, Kr.  Outputs
+// acoef, bcoef (m x nb, ld m) and omega (host, ascending).  Returns BDG_EBREAKDOWN when the
+// usable rank is below nb or a projected matrix is not numerically positive definite.
+bdg_status rr_once(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const double2* Gg,
+                         const double2* Br, const double2* Mr, const double2* Kr, double2* acoef, double2* bcoef,
+                         std::vector<double>& omega, double rtol, double eps) {
+    double2* T = w.buf[5];
+    double2* Rf = w.buf[6];
+    double2* Rg = w.buf[7];
+    double2* B = w.buf[8];
+    double2* V3 = w.buf[9];
+    double2* Cf = w.buf[10];
+    double2* Cg = w.buf[11];
+    double2* X1 = w.buf[12];
+    double2* X2 = w.buf[13];
+    int rf = 0, rg = 0;
+    BDG_TRY(orth_factor(c, w, m, Gf, T, Rf, w.s[0], rtol, &rf));
+    BDG_TRY(orth_factor(c, w, m, Gg, T, Rg, w.s[1], rtol, &rg));
+    if (rf < nb || rg < nb) return ctx_fail(c, BDG_EBREAKDOWN, "basis rank below block size");
+    // B = Rg^H Br Rf (rg x rf)
+    BDG_TRY(small_gemm(c, 0, 0, m, rf, m, ONE, Br, m, Rf, m, ZERO, T, m));
+    BDG_TRY(small_gemm(c, 1, 0, rg, rf, m, ONE, Rg, m, T, m, ZERO, B, m));
+    BDG_TRY(small_svd(c, rg, rf, B, m, V3, m, w.s[2]));
+    std::vector<double> s3(rf);
+    BDG_TRY(d2h(c, s3.data(), w.s[2], rf * sizeof(double)));
+    int r = 0;
+    while (r < rf && r < rg && s3[r] > eps) ++r;
+    if (r < nb) return ctx_fail(c, BDG_EBREAKDOWN, "bi-orthogonal rank below block size");
+    // Cf = Rf V3(:, :r) s^-1/2 ; Cg = Rg (U s)(:, :r) s^-3/2
+    BDG_TRY(small_gemm(c, 0, 0, m, r, rf, ONE, Rf, m, V3, m, ZERO, Cf, m));
+    BDG_TRY(small_colpow(c, m, r, Cf, m, w.s[2], -0.5));
+    BDG_TRY(small_gemm(c, 0, 0, m, r, rg, ONE, Rg, m, B, m, ZERO, Cg, m));
+    BDG_TRY(small_colpow(c, m, r, Cg, m, w.s[2], -1.5));
+    // Mt = Cf^H Mr Cf -> X1 ; Kt = Cg^H Kr Cg -> X2
+    BDG_TRY(small_gemm(c, 0, 0, m, r, m, ONE, Mr, m, Cf, m, ZERO, T, m));
+    BDG_TRY(small_gemm(c, 1, 0, r, r, m, ONE, Cf, m, T, m, ZERO, X1, m));
+    BDG_TRY(small_gemm(c, 0, 0, m, r, m, ONE, Kr, m, Cg, m, ZERO, T, m));
+    BDG_TRY(small_gemm(c, 1, 0, r, r, m, ONE, Cg, m, T, m, ZERO, X2, m));
+    hipLaunchKernelGGL(k_small_herm, dim3((unsigned)((r + 127) / 128), (unsigned)r), dim3(128), 0, c->stream, r, X1, m);
+    hipLaunchKernelGGL(k_small_herm, dim3((unsigned)((r + 127) / 128), (unsigned)r), dim3(128), 0, c->stream, r, X2, m);
+    BDG_TRY(small_cholesky(c, r, X1, m, w.info));
+    BDG_TRY(small_cholesky(c, r, X2, m, w.info + 1));
+    // G = L_K^H L_M -> B ; SVD -> V3, s[3]
+    BDG_TRY(small_gemm(c, 1, 0, r, r, r, ONE, X2, m, X1, m, ZERO, B, m));
+    BDG_TRY(small_svd(c, r, r, B, m, V3, m, w.s[3]));
+    int info[2];
+    std::vector<double> s4(r);
+    BDG_TRY(d2h(c, info, w.info, 2 * sizeof(int)));
+    if (debug_on())
+        fprintf(stderr, "[bdg rr] m=%d rf=%d rg=%d r=%d cos[min]=%.3e cos[r-1]=%.3e chol=(%d,%d) rtol=%.1e eps=%.1e\n", m,
+                rf, rg, r, s3[std::min(rf, rg) - 1], s3[r - 1], info[0], info[1], rtol, eps);
+    if (info[0] || info[1]) return ctx_fail(c, BDG_EBREAKDOWN, "projected matrix not positive definite");
+    BDG_TRY(d2h(c, s4.data(), w.s[3], r * sizeof(double)));
+    // the nb smallest singular values, ascending
+    std::vector<int> idx(nb);
+    std::vector<double> scl(2 * nb);
+    omega.assign(nb, 0.0);
+    for (int t = 0; t < nb; ++t) {
+        const int j = r - 1 - t;
+        idx[t] = j;
+        const double om = s4[j];
+        if (!(om > 0)) return ctx_fail(c, BDG_EBREAKDOWN, "zero projected frequency");
+        omega[t] = om;
+        scl[t] = 1.0 / (om * std::sqrt(4.0 * om));      // u = G col / sigma, times 1/sqrt(4 w)
+        scl[nb + t] = 1.0 / std::sqrt(4.0 * om);
+    }
+    BDG_TRY(h2d(c, w.idx, idx.data(), nb * sizeof(int)));
+    BDG_TRY(h2d(c, w.dscale, scl.data(), 2 * nb * sizeof(double)));
+    // A1 = Cf L_K (m x r) -> T ; a = A1 Gsel
+    BDG_TRY(small_gemm(c, 0, 0, m, r, r, ONE, Cf, m, X2, m, ZERO, T, m));
+    hipLaunchKernelGGL(k_small_gather, dim3((unsigned)nb), dim3(256), 0, c->stream, r, nb, (const double2*)B, m,
+                       (const int*)w.idx, (const double*)w.dscale, Rf, m);
+    BDG_TRY(small_gemm(c, 0, 0, m, nb, r, ONE, T, m, Rf, m, ZERO, acoef, m));
+    // B1 = Cg L_M -> T ; b = B1 Vsel
+    BDG_TRY(small_gemm(c, 0, 0, m, r, r, ONE, Cg, m, X1, m, ZERO, T, m));
+    hipLaunchKernelGGL(k_small_gather, dim3((unsigned)nb), dim3(256), 0, c->stream, r, nb, (const double2*)V3, m,
+                       (const int*)w.idx, (const double*)(w.dscale + nb), Rg, m);
+    BDG_TRY(small_gemm(c, 0, 0, m, nb, r, ONE, T, m, Rg, m, ZERO, bcoef, m));
+    return hip_check(c, hipGetLastError(), "rayleigh_ritz");
+}
+
+// rr_once with escalating cut-offs: rounding in the projected matrices can make them
+// indefinite along nearly dependent directions; dropping those directions (larger rtol,
+// eps) restores definiteness without changing the spanned space's useful part.
+bdg_status rayleigh_ritz(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const double2* Gg,
+                         const double2* Br, const double2* Mr, const double2* Kr, double2* acoef, double2* bcoef,
+                         std::vector<double>& omega, double rtol, double eps) {
+    bdg_status st = BDG_OK;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        st = rr_once(c, w, m, nb, Gf, Gg, Br, Mr, Kr, acoef, bcoef, omega, rtol, eps);
+        if (st != BDG_EBREAKDOWN) return st;
+        rtol *= 100.0;
+        eps *= 100.0;
+    }
+    return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// Block storage of the iteration: four arrays (S_f, S_g, H_+ S_f, H_- S_g) of four slots of
+// nb columns (nh complex each); three slots hold F, W, P and one is free for the update.
+// ---------------------------------------------------------------------------------------
+struct Basis {
+    long long nh = 0;
+    int nb = 0;
+    double2* arr[4] = {};
+    int slotF = 0, slotW = 1, slotP = -1, slotFree = 2, slotFree2 = 3;
+    double2* col(int a, int slot) const { return arr[a] + (long long)slot * nb * nh; }
+};
+enum { SF = 0, SG = 1, HSF = 2, HSG = 3 };
+
+// images of a block: [H_- g; H_+ f] for columns f (arr SF slot) and g (arr SG slot)
+bdg_status apply64(bdg_ctx* c, int ncols, const double2* f, const double2* g, long long nh, double2* Hf,
+                   double2* Hg) {
+    BlockRef<const double2> X{f, g, nh};
+    BlockRef<double2> Y{Hg, Hf, nh};
+    return launch_apply<double>(c, BDG_FORM_FG, 0, ncols, X, Y);
+}
+
+// X (nh x ncols) -= Q (Q^H X h^d) with Q orthonormal (nh x q)
+bdg_status project_out(bdg_ctx* c, Small& w, long long nh, const double2* Q, int q, double2* X, int ncols) {
+    if (q == 0 || ncols == 0) return BDG_OK;
+    double2* Cq = w.buf[4];
+    BDG_TRY(gram<double2, double2>(c, nh, q, ncols, Q, nh, X, nh, -c->hd, Cq, q, 0));
+    Seg s{Q, q};
+    return update(c, nh, &s, 1, nh, Cq, q, ncols, 1.0, X, nh);
+}
+
+bdg_status unit_columns(bdg_ctx* c, long long nh, int ncols, double2* X, double2* HX, double* nrm_dev) {
+    BDG_TRY(colnorm2(c, nh, ncols, X, nh, nrm_dev));
+    hipLaunchKernelGGL(k_cols_scale, grid_cols(nh, ncols), dim3(256), 0, c->stream, nh, ncols, X, nh,
+                       (const double*)nrm_dev, 1);
+    if (HX)
+        hipLaunchKernelGGL(k_cols_scale, grid_cols(nh, ncols), dim3(256), 0, c->stream, nh, ncols, HX, nh,
+                           (const double*)nrm_dev, 1);
+    return hip_check(c, hipGetLastError(), "unit_columns");
+}
+
+// orthonormal basis (nh x r) of the columns of X (nh x p) into Out; rank by rtol on the Gram
+bdg_status orthonormalize(bdg_ctx* c, Small& w, long long nh, const double2* X, int p, double2* Out, double rtol,
+                          int* r_out) {
+    *r_out = 0;
+    if (p == 0) return BDG_OK;
+    BDG_TRY(gram<double2, double2>(c, nh, p, p, X, nh, X, nh, c->hd, w.buf[0], p, 1));
+    int r = 0;
+    BDG_TRY(orth_factor(c, w, p, w.buf[0], w.buf[1], w.buf[2], w.s[0], rtol, &r));
+    Seg s{X, p};
+    BDG_TRY(update(c, nh, &s, 1, nh, w.buf[2], p, r, 0.0, Out, nh));
+    *r_out = r;
+    return BDG_OK;
+}
+
+double host_dot_re(bdg_ctx* c, Small& w, long long nh, const double2* a, const double2* b, bdg_status* st) {
+    double2 v{0, 0};
+    *st = gram<double2, double2>(c, nh, 1, 1, a, nh, b, nh, c->hd, w.buf[3], 1, 0);
+    if (*st == BDG_OK) *st = d2h(c, &v, w.buf[3], sizeof(double2));
+    return v.x;
+}
+
+// Projected preconditioned CG for H_+ x = b on span(Np)^perp (Jordan partners).
+bdg_status pcg_hplus(bdg_ctx* c, Small& w, long long nh, const double2* Np, int np, const double2* b, double2* x,
+                     double2* ws, double shift, double tol, int max_iter) {
+    double2* r = ws;
+    double2* z = ws + nh;
+    double2* p = ws + 2 * nh;
+    double2* Ap = ws + 3 * nh;
+    double2* tmp = ws + 4 * nh;
+    const dim3 g1 = grid_cols(nh, 1);
+    BDG_HIP(c, hipMemsetAsync(x, 0, nh * sizeof(double2), c->stream));
+    BDG_HIP(c, hipMemcpyAsync(r, b, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    BDG_TRY(project_out(c, w, nh, Np, np, r, 1));
+    BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z, shift));
+    BDG_TRY(project_out(c, w, nh, Np, np, z, 1));
+    BDG_HIP(c, hipMemcpyAsync(p, z, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    bdg_status st;
+    double rz = host_dot_re(c, w, nh, z, r, &st);
+    BDG_TRY(st);
+    const double bnorm = std::sqrt(std::max(0.0, host_dot_re(c, w, nh, r, r, &st)));
+    BDG_TRY(st);
+    if (bnorm == 0) return BDG_OK;
+    for (int it = 0; it < max_iter; ++it) {
+        BDG_TRY(apply64(c, 1, p, p, nh, Ap, tmp));
+        BDG_TRY(project_out(c, w, nh, Np, np, Ap, 1));
+        const double pAp = host_dot_re(c, w, nh, Ap, p, &st);
+        BDG_TRY(st);
+        if (!(pAp > 0)) return ctx_fail(c, BDG_EBREAKDOWN, "Jordan-partner solve: H_+ not positive");
+        const double alpha = rz / pAp;
+        hipLaunchKernelGGL(k_axpy, g1, dim3(256), 0, c->stream, nh, cmk<double2>(alpha, 0.0), (const double2*)p, x);
+        hipLaunchKernelGGL(k_axpy, g1, dim3(256), 0, c->stream, nh, cmk<double2>(-alpha, 0.0), (const double2*)Ap, r);
+        const double rn = std::sqrt(std::max(0.0, host_dot_re(c, w, nh, r, r, &st)));
+        BDG_TRY(st);
+        if (rn <= tol * bnorm) return BDG_OK;
+        BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z, shift));
+        BDG_TRY(project_out(c, w, nh, Np, np, z, 1));
+        const double rz_new = host_dot_re(c, w, nh, z, r, &st);
+        BDG_TRY(st);
+        hipLaunchKernelGGL(k_xpby, g1, dim3(256), 0, c->stream, nh, (const double2*)z, cmk<double2>(rz_new / rz, 0.0), p);
+        rz = rz_new;
+    }
+    return ctx_fail(c, BDG_ENOCONV, "Jordan-partner solve did not converge");
+}
+
+struct Deflation {
+    double2* Nm = nullptr;   // nh x pm, orthonormal basis of ns(H_-) (f-space deflation)
+    int pm = 0;
+    double2* Qg = nullptr;   // nh x pg, ns(H_+) + Jordan partners (g-space deflation)
+    int pg = 0;
+};
+
+bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double shift, double null_tol) {
+    const long long npts = c->npts, nh = 3 * npts;
+    double2* cand = nullptr;
+    double2* img = nullptr;
+    double2* ws = nullptr;
+    BDG_TRY(ctx_alloc(c, (void**)&cand, 4 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&img, 8 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&ws, 5 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&d.Nm, 3 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&d.Qg, 4 * nh * sizeof(double2)));
+    hipLaunchKernelGGL(k_candidates, dim3(1024), dim3(256), 0, c->stream, npts, (const double*)c->phi, cand);
+    BDG_HIP(c, hipGetLastError());
+    // images: [H_- c; H_+ c] for each candidate c (taken as both f and g)
+    double2* Hm = img;
+    double2* Hp = img + 4 * nh;
+    BDG_TRY(apply64(c, 4, cand, cand, nh, Hp, Hm));
+    double nc[4], nm[4], np_[4];
+    BDG_TRY(colnorm2(c, nh, 4, cand, nh, w.s[0]));
+    BDG_TRY(colnorm2(c, nh, 4, Hm, nh, w.s[1]));
+    BDG_TRY(colnorm2(c, nh, 4, Hp, nh, w.s[2]));
+    BDG_TRY(d2h(c, nc, w.s[0], 4 * sizeof(double)));
+    BDG_TRY(d2h(c, nm, w.s[1], 4 * sizeof(double)));
+    BDG_TRY(d2h(c, np_, w.s[2], 4 * sizeof(double)));
+    const double cmax = std::max(std::max(nc[0], nc[1]), std::max(nc[2], nc[3]));
+    double2* keep = ws;            // up to 3 columns (reuses PCG space before the solves)
+    int km = 0;
+    for (int j = 0; j < 3; ++j)
+        if (nc[j] > 1e-24 * cmax && std::sqrt(nm[j]) <= null_tol * std::sqrt(nc[j])) {
+            BDG_HIP(c, hipMemcpyAsync(keep + km * nh, cand + j * nh, nh * sizeof(double2), hipMemcpyDeviceToDevice,
+                                      c->stream));
+            ++km;
+        }
+    BDG_TRY(orthonormalize(c, w, nh, keep, km, d.Nm, 1e-10, &d.pm));
+    // ns(H_+) candidate: K Phi
+    double2* Np = img;             // reuse
+    int pp = 0;
+    if (nc[3] > 1e-20 * cmax && std::sqrt(np_[3]) <= null_tol * std::sqrt(nc[3])) {
+        BDG_TRY(orthonormalize(c, w, nh, cand + 3 * nh, 1, Np, 1e-10, &pp));
+    }
+    // sources of the Jordan partners: part of N_- orthogonal to N_+
+    double2* src = img + nh;       // up to 3 columns
+    BDG_HIP(c, hipMemcpyAsync(keep, d.Nm, d.pm * nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    BDG_TRY(project_out(c, w, nh, Np, pp, keep, d.pm));
+    int ps = 0;
+    BDG_TRY(orthonormalize(c, w, nh, keep, d.pm, src, 1e-8, &ps));
+    // partners into the columns after N_+
+    double2* qcols = cand;         // [N_+, partners], up to 4 columns
+    if (pp) BDG_HIP(c, hipMemcpyAsync(qcols, Np, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    for (int j = 0; j < ps; ++j)
+        BDG_TRY(pcg_hplus(c, w, nh, Np, pp, src + j * nh, qcols + (pp + j) * nh, ws, shift, 1e-13, 5000));
+    BDG_TRY(orthonormalize(c, w, nh, qcols, pp + ps, d.Qg, 1e-10, &d.pg));
+    if (debug_on()) {
+        fprintf(stderr, "[bdg deflation] |c|^2=(%.3e %.3e %.3e %.3e) |H_- c|^2=(%.3e %.3e %.3e %.3e) |H_+ c|^2=(%.3e %.3e %.3e %.3e)\n",
+                nc[0], nc[1], nc[2], nc[3], nm[0], nm[1], nm[2], nm[3], np_[0], np_[1], np_[2], np_[3]);
+        fprintf(stderr, "[bdg deflation] N_- dim %d, N_+ dim %d, partners %d, Q_g dim %d\n", d.pm, pp, ps, d.pg);
+    }
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    ctx_free(c, cand);
+    ctx_free(c, img);
+    ctx_free(c, ws);
+    return BDG_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+// bdg_biortho
+// =====================================================================================
+extern "C" bdg_status bdg_biortho(bdg_ctx* c, int nvec, void* F_dev, void* G_dev, double* sigma, int* rank) {
+    if (!c) return BDG_EINVAL;
+    if (nvec <= 0 || nvec > 512 || !F_dev || !G_dev) return ctx_fail(c, BDG_EINVAL, "bdg_biortho: bad arguments");
+    const long long nh = 3 * c->npts;
+    Small w;
+    bdg_status st = small_alloc(c, w, nvec);
+    if (st != BDG_OK) { small_free(c, w); return st; }
+    double2* F = (double2*)F_dev;
+    double2* G = (double2*)G_dev;
+    double2* tmp = nullptr;
+    st = ctx_alloc(c, (void**)&tmp, (size_t)nvec * nh * sizeof(double2));
+    auto run = [&]() -> bdg_status {
+        double2* B = w.buf[0];
+        double2* V = w.buf[1];
+        double2* Cg = w.buf[2];
+        BDG_TRY(gram<double2, double2>(c, nh, nvec, nvec, G, nh, F, nh, c->hd, B, nvec, 0));
+        BDG_TRY(small_svd(c, nvec, nvec, B, nvec, V, nvec, w.s[0]));
+        std::vector<double> s(nvec);
+        BDG_TRY(d2h(c, s.data(), w.s[0], nvec * sizeof(double)));
+        int r = 0;
+        while (r < nvec && s[r] > 1e-12 * s[0] && s[r] > 0) ++r;
+        // C_f = V s^-1/2 ; C_g = (U s) s^-3/2 ; dropped columns -> 0
+        BDG_TRY(small_colpow(c, nvec, nvec, V, nvec, w.s[0], -0.5));
+        BDG_TRY(small_copy(c, nvec, nvec, B, nvec, Cg, nvec));
+        BDG_TRY(small_colpow(c, nvec, nvec, Cg, nvec, w.s[0], -1.5));
+        if (r < nvec) {
+            std::vector<double2> z((size_t)nvec * (nvec - r), cmk<double2>(0, 0));
+            BDG_TRY(h2d(c, V + (size_t)r * nvec, z.data(), z.size() * sizeof(double2)));
+            BDG_TRY(h2d(c, Cg + (size_t)r * nvec, z.data(), z.size() * sizeof(double2)));
+        }
+        Seg sf{F, nvec}, sg{G, nvec};
+        BDG_TRY(update(c, nh, &sf, 1, nh, V, nvec, nvec, 0.0, tmp, nh));
+        BDG_HIP(c, hipMemcpyAsync(F, tmp, (size_t)nvec * nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+        BDG_TRY(update(c, nh, &sg, 1, nh, Cg, nvec, nvec, 0.0, tmp, nh));
+        BDG_HIP(c, hipMemcpyAsync(G, tmp, (size_t)nvec * nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+        BDG_HIP(c, hipStreamSynchronize(c->stream));
+        if (sigma) std::memcpy(sigma, s.data(), nvec * sizeof(double));
+        if (rank) *rank = r;
+        return BDG_OK;
+    };
+    if (st == BDG_OK) st = run();
+    ctx_free(c, tmp);
+    small_free(c, w);
+    return st;
+}
+
+// =====================================================================================
+// bdg_eigs
+// =====================================================================================
+namespace {
+
+struct EigsOpts {
+    double shift = 20.0;        // preconditioner shift sigma
+    double rtol = 1e-13;        // rank cut-off of the per-basis Gram eigenvalues
+    double eps = 1e-10;         // cut-off of the pairing cosines
+    double null_tol = 1e-6;     // nullspace candidate test
+    double refresh_tol = 1e-5;  // mixed precision: refresh images once this residual is reached
+    int refresh_every = 25;     // float64 re-projection and image refresh period (iterations)
+    int stall_iters = 30;       // mixed form: switch to float64 applies after this many
+                                // iterations without halving the residual
+    double rtol32 = 1e-10;      // cut-offs while images carry float32 rounding
+    double eps32 = 1e-7;
+};
+
+bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const void* X0_dev,
+                     unsigned long long seed, double* omega_out, void* UV_dev, double* res_out, int* iters_out) {
+    const EigsOpts opt;
+    const long long npts = c->npts, nh = 3 * npts;
+    const bool mixed = c->prob.precision == BDG_FP32_APPLY;
+    const int m = 3 * nb;
+    auto t_start = std::chrono::steady_clock::now();
+    for (double& s : c->stats) s = 0;
+    // ------------------------------------------------------------------ allocation
+    Small w;
+    BDG_TRY(small_alloc(c, w, std::max(m, 8)));
+    Basis S;
+    S.nh = nh;
+    S.nb = nb;
+    for (int a = 0; a < 4; ++a) BDG_TRY(ctx_alloc(c, (void**)&S.arr[a], 4 * (size_t)nb * nh * sizeof(double2)));
+    float2* w32 = nullptr;
+    float2* y32 = nullptr;
+    if (mixed) {
+        BDG_TRY(ctx_alloc(c, (void**)&w32, 2 * (size_t)nb * nh * sizeof(float2)));
+        BDG_TRY(ctx_alloc(c, (void**)&y32, 2 * (size_t)nb * nh * sizeof(float2)));
+    }
+    double2* acoef = nullptr;
+    double2* bcoef = nullptr;
+    double* dvec = nullptr;
+    BDG_TRY(ctx_alloc(c, (void**)&acoef, (size_t)m * nb * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&bcoef, (size_t)m * nb * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&dvec, 8 * (size_t)nb * sizeof(double)));
+    double* d_om = dvec;
+    double* d_n = dvec + nb;      // 4 nb norms
+    // ------------------------------------------------------------------ deflation
+    Deflation D;
+    BDG_TRY(build_deflation(c, w, D, opt.shift, opt.null_tol));
+    auto t_setup = std::chrono::steady_clock::now();
+    c->stats[6] = std::chrono::duration<double, std::milli>(t_setup - t_start).count();
+    // ------------------------------------------------------------------ start block
+    S.slotF = 0; S.slotW = 1; S.slotP = -1; S.slotFree = 2; S.slotFree2 = 3;
+    double2* F = S.col(SF, S.slotF);
+    double2* G = S.col(SG, S.slotF);
+    if (X0_dev) {
+        BDG_HIP(c, hipMemcpy2DAsync(F, nh * sizeof(double2), X0_dev, 2 * nh * sizeof(double2), nh * sizeof(double2), nb,
+                                    hipMemcpyDeviceToDevice, c->stream));
+        BDG_HIP(c, hipMemcpy2DAsync(G, nh * sizeof(double2), (const double2*)X0_dev + nh, 2 * nh * sizeof(double2),
+                                    nh * sizeof(double2), nb, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        hipLaunchKernelGGL(k_randn, dim3(2048), dim3(256), 0, c->stream, (long long)nb * nh, seed, F);
+        hipLaunchKernelGGL(k_randn, dim3(2048), dim3(256), 0, c->stream, (long long)nb * nh, seed ^ 0x5851F42D4C957F2DULL, G);
+    }
+    BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, F, nb));
+    BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, G, nb));
+    double napply64 = 0, napply32 = 0;
+    BDG_TRY(apply64(c, nb, F, G, nh, S.col(HSF, S.slotF), S.col(HSG, S.slotF)));
+    napply64 += nb;
+    double2* Gf = w.buf[0];
+    double2* Gg = w.buf[1];
+    double2* Br = w.buf[2];
+    double2* Mr = w.buf[3];
+    double2* Kr = w.buf[4];
+    std::vector<double> om;
+    auto grams = [&](const Seg* sf, const Seg* sg, const Seg* hf, const Seg* hg, int ns, int ldc) -> bdg_status {
+        BDG_TRY(gram_seg(c, nh, sf, ns, nh, sf, ns, nh, c->hd, Gf, ldc, 1));
+        BDG_TRY(gram_seg(c, nh, sg, ns, nh, sg, ns, nh, c->hd, Gg, ldc, 1));
+        BDG_TRY(gram_seg(c, nh, sg, ns, nh, sf, ns, nh, c->hd, Br, ldc, 0));
+        BDG_TRY(gram_seg(c, nh, sf, ns, nh, hf, ns, nh, c->hd, Mr, ldc, 1));
+        BDG_TRY(gram_seg(c, nh, sg, ns, nh, hg, ns, nh, c->hd, Kr, ldc, 1));
+        return BDG_OK;
+    };
+    // re-deflate F, G (and P) and recompute their images with float64 applies
+    auto refresh = [&](double2* F_, double2* G_, double2* HF_, double2* HG_) -> bdg_status {
+        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, F_, nb));
+        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, G_, nb));
+        BDG_TRY(apply64(c, nb, F_, G_, nh, HF_, HG_));
+        napply64 += nb;
+        if (S.slotP >= 0) {
+            double2* Pf = S.col(SF, S.slotP);
+            double2* Pg = S.col(SG, S.slotP);
+            BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Pf, nb));
+            BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Pg, nb));
+            BDG_TRY(apply64(c, nb, Pf, Pg, nh, S.col(HSF, S.slotP), S.col(HSG, S.slotP)));
+            napply64 += nb;
+        }
+        return BDG_OK;
+    };
+    {
+        Seg sf{F, nb}, sg{G, nb}, hf{S.col(HSF, S.slotF), nb}, hg{S.col(HSG, S.slotF), nb};
+        BDG_TRY(grams(&sf, &sg, &hf, &hg, 1, nb));
+        BDG_TRY(rayleigh_ritz(c, w, nb, nb, Gf, Gg, Br, Mr, Kr, acoef, bcoef, om, opt.rtol, opt.eps));
+        const int s_new = S.slotW;
+        for (int a = 0; a < 4; ++a) {
+            Seg src{S.col(a, S.slotF), nb};
+            BDG_TRY(update(c, nh, &src, 1, nh, (a == SF || a == HSF) ? acoef : bcoef, nb, nb, 0.0, S.col(a, s_new), nh));
+        }
+        S.slotW = S.slotF;
+        S.slotF = s_new;
+    }
+    int it = 0;
+    int last_refresh = 0, recoveries = 0, best_it = 0;
+    double best_r = 1e300;
+    bool switch64 = false;
+    bool converged = false;
+    bool refreshed = false;
+    int certifications = 0;
+    bool force64 = false;
+    std::vector<double> res(nb, 1.0), hn(4 * nb);
+    bdg_status final_status = BDG_ENOCONV;
+    double t_apply = 0, t_prec = 0, t_gram = 0, t_small = 0, t_upd = 0;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms_since = [&](std::chrono::steady_clock::time_point t0) {
+        return std::chrono::duration<double, std::milli>(now() - t0).count();
+    };
+    const bool timing = true;
+    auto sync_if = [&]() -> bdg_status {
+        if (timing) BDG_HIP(c, hipStreamSynchronize(c->stream));
+        return BDG_OK;
+    };
+    for (it = 1; it <= max_iter; ++it) {
+        F = S.col(SF, S.slotF);
+        G = S.col(SG, S.slotF);
+        double2* HF = S.col(HSF, S.slotF);
+        double2* HG = S.col(HSG, S.slotF);
+        double2* Wf = S.col(SF, S.slotW);
+        double2* Wg = S.col(SG, S.slotW);
+        auto t0 = now();
+        // residual directions and norms
+        BDG_TRY(h2d(c, d_om, om.data(), nb * sizeof(double)));
+        hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)HF, nh,
+                           (const double2*)G, nh, (const double*)d_om, Wf, nh);
+        hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)HG, nh,
+                           (const double2*)F, nh, (const double*)d_om, Wg, nh);
+        BDG_TRY(colnorm2(c, nh, nb, Wf, nh, d_n));
+        BDG_TRY(colnorm2(c, nh, nb, Wg, nh, d_n + nb));
+        BDG_TRY(colnorm2(c, nh, nb, F, nh, d_n + 2 * nb));
+        BDG_TRY(colnorm2(c, nh, nb, G, nh, d_n + 3 * nb));
+        BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
+        double rmax = 0;
+        for (int j = 0; j < nb; ++j) {
+            res[j] = std::sqrt(hn[j] + hn[nb + j]) / (std::fabs(om[j]) * std::sqrt(hn[2 * nb + j] + hn[3 * nb + j]));
+            if (j < k) rmax = std::max(rmax, res[j]);
+        }
+        if (!(rmax == rmax)) return ctx_fail(c, BDG_EBREAKDOWN, "non-finite residual");
+        if (debug_on())
+            fprintf(stderr, "[bdg it %d] omega0=%.12f omega_k=%.12f res_max(k)=%.3e res0=%.3e\n", it, om[0], om[k - 1], rmax,
+                    res[0]);
+        // mixed form: float32 applies of the correction block until the residual reaches
+        // refresh_tol or stops decreasing (the float32 rounding of the images sets a floor
+        // near eps32 ||H|| / omega); then float64 applies finish the solve
+        if (mixed && !force64) {
+            if (rmax < best_r * 0.5) { best_r = rmax; best_it = it; }
+            if (rmax <= opt.refresh_tol || it - best_it > opt.stall_iters) switch64 = true;
+        }
+        const bool want_refresh = switch64 || (it - last_refresh >= opt.refresh_every);
+        if (want_refresh) {
+            // re-project the basis off the generalized nullspace and recompute its images in
+            // float64 (bounds the drift of the recurrence-updated images; in the mixed form
+            // it also removes the float32 rounding the images carry)
+            BDG_TRY(refresh(F, G, HF, HG));
+            if (switch64) { force64 = true; refreshed = true; switch64 = false; }
+            last_refresh = it;
+            --it;
+            continue;
+        }
+        if (rmax <= tol) {
+            // certify with a float64 apply of the current block
+            double2* CF = S.col(HSF, S.slotFree);
+            double2* CG = S.col(HSG, S.slotFree);
+            BDG_TRY(apply64(c, nb, F, G, nh, CF, CG));
+            napply64 += nb;
+            hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)CF, nh,
+                               (const double2*)G, nh, (const double*)d_om, Wf, nh);
+            hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)CG, nh,
+                               (const double2*)F, nh, (const double*)d_om, Wg, nh);
+            BDG_TRY(colnorm2(c, nh, nb, Wf, nh, d_n));
+            BDG_TRY(colnorm2(c, nh, nb, Wg, nh, d_n + nb));
+            BDG_TRY(d2h(c, hn.data(), d_n, 2 * nb * sizeof(double)));
+            double cmax = 0;
+            for (int j = 0; j < nb; ++j) {
+                res[j] = std::sqrt(hn[j] + hn[nb + j]) / (std::fabs(om[j]) * std::sqrt(hn[2 * nb + j] + hn[3 * nb + j]));
+                if (j < k) cmax = std::max(cmax, res[j]);
+            }
+            if (cmax <= tol) {
+                converged = true;
+                break;
+            }
+            // images drifted: refresh and continue (float64 corrections from now on)
+            BDG_TRY(refresh(F, G, HF, HG));
+            last_refresh = it;
+            force64 = true;
+            if (++certifications > 4) break;
+            --it;
+            continue;
+        }
+        // preconditioned corrections (the preconditioner's precision only affects the rate)
+        if (mixed) {
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wf, nh, w32, nh);
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wg, nh,
+                               w32 + (size_t)nb * nh, nh);
+            BDG_TRY(launch_precond<float>(c, 6 * nb, 3, nh, w32, w32, opt.shift));
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const float2*)w32, nh, Wf, nh);
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb,
+                               (const float2*)(w32 + (size_t)nb * nh), nh, Wg, nh);
+        } else {
+            BDG_TRY(launch_precond<double>(c, 3 * nb, 3, nh, Wf, Wf, opt.shift));
+            BDG_TRY(launch_precond<double>(c, 3 * nb, 3, nh, Wg, Wg, opt.shift));
+        }
+        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Wf, nb));
+        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nb));
+        BDG_TRY(unit_columns(c, nh, nb, Wf, nullptr, d_n));
+        BDG_TRY(unit_columns(c, nh, nb, Wg, nullptr, d_n + nb));
+        BDG_TRY(sync_if());
+        t_prec += ms_since(t0);
+        auto t1 = now();
+        double2* HWf = S.col(HSF, S.slotW);
+        double2* HWg = S.col(HSG, S.slotW);
+        if (mixed && !force64) {
+            float2* wf32 = w32;
+            float2* wg32 = w32 + (size_t)nb * nh;
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wf, nh, wf32, nh);
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wg, nh, wg32, nh);
+            BlockRef<const float2> X{wf32, wg32, nh};
+            BlockRef<float2> Y{y32, y32 + (size_t)nb * nh, nh};   // lo: H_- W_g, hi: H_+ W_f
+            BDG_TRY(launch_apply<float>(c, BDG_FORM_FG, 0, nb, X, Y));
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const float2*)y32, nh, HWg, nh);
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb,
+                               (const float2*)(y32 + (size_t)nb * nh), nh, HWf, nh);
+            napply32 += nb;
+        } else {
+            BDG_TRY(apply64(c, nb, Wf, Wg, nh, HWf, HWg));
+            napply64 += nb;
+        }
+        BDG_TRY(sync_if());
+        t_apply += ms_since(t1);
+        auto t2 = now();
+        // Gram matrices of [F, W, P]
+        const int ns = S.slotP >= 0 ? 3 : 2;
+        const int mc = ns * nb;
+        Seg sf[3] = {{F, nb}, {Wf, nb}, {S.slotP >= 0 ? S.col(SF, S.slotP) : nullptr, nb}};
+        Seg sg[3] = {{G, nb}, {Wg, nb}, {S.slotP >= 0 ? S.col(SG, S.slotP) : nullptr, nb}};
+        Seg hf[3] = {{HF, nb}, {HWf, nb}, {S.slotP >= 0 ? S.col(HSF, S.slotP) : nullptr, nb}};
+        Seg hg[3] = {{HG, nb}, {HWg, nb}, {S.slotP >= 0 ? S.col(HSG, S.slotP) : nullptr, nb}};
+        BDG_TRY(grams(sf, sg, hf, hg, ns, mc));
+        BDG_TRY(sync_if());
+        t_gram += ms_since(t2);
+        auto t3 = now();
+        const bool f32img = mixed && !refreshed && !force64;
+        std::vector<double> om_prev = om;
+        bdg_status rst = rayleigh_ritz(c, w, mc, nb, Gf, Gg, Br, Mr, Kr, acoef, bcoef, om,
+                                       f32img ? opt.rtol32 : opt.rtol, f32img ? opt.eps32 : opt.eps);
+        if (rst == BDG_EBREAKDOWN && recoveries < 8) {
+            // projected problem lost definiteness: refresh the basis, drop P, and redo the step
+            ++recoveries;
+            om = om_prev;
+            BDG_TRY(refresh(F, G, HF, HG));
+            last_refresh = it;
+            S.slotFree2 = S.slotP;     // P is discarded
+            S.slotP = -1;
+            force64 = force64 || mixed;
+            continue;
+        }
+        if (rst != BDG_OK) { final_status = rst; break; }
+        t_small += ms_since(t3);
+        auto t4 = now();
+        // updates: P_new = [W, P] a[nb:], F_new = [F, W, P] a
+        const int dst_P = S.slotFree, dst_F = S.slotW;
+        for (int a = 0; a < 4; ++a) {
+            const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
+            const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
+            BDG_TRY(update(c, nh, seg + 1, ns - 1, nh, coef + nb, mc, nb, 0.0, S.col(a, dst_P), nh));
+        }
+        for (int a = 0; a < 4; ++a) {
+            const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
+            const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
+            BDG_TRY(update(c, nh, seg, ns, nh, coef, mc, nb, 0.0, S.col(a, dst_F), nh));
+        }
+        // rotate slot roles
+        const int oldF = S.slotF, oldP = S.slotP;
+        S.slotF = dst_F;
+        S.slotP = dst_P;
+        S.slotW = oldF;
+        S.slotFree = (oldP >= 0) ? oldP : S.slotFree2;
+        S.slotFree2 = -1;
+        // unit columns of P (and images, same factor)
+        BDG_TRY(unit_columns(c, nh, nb, S.col(SF, S.slotP), S.col(HSF, S.slotP), d_n));
+        BDG_TRY(unit_columns(c, nh, nb, S.col(SG, S.slotP), S.col(HSG, S.slotP), d_n + nb));
+        BDG_TRY(sync_if());
+        t_upd += ms_since(t4);
+    }
+    if (converged) final_status = BDG_OK;
+    F = S.col(SF, S.slotF);
+    G = S.col(SG, S.slotF);
+    // outputs
+    const int kk = std::min(k, (int)om.size());
+    if (omega_out) for (int j = 0; j < kk; ++j) omega_out[j] = om[j];
+    if (res_out) for (int j = 0; j < kk; ++j) res_out[j] = res[j];
+    if (iters_out) *iters_out = std::min(it, max_iter);
+    if (UV_dev) {
+        // exact <f, g> = 1/4 through one real scale per column
+        BDG_TRY(gram<double2, double2>(c, nh, kk, kk, G, nh, F, nh, c->hd, w.buf[0], kk, 0));
+        std::vector<double2> fg((size_t)kk * kk);
+        BDG_TRY(d2h(c, fg.data(), w.buf[0], fg.size() * sizeof(double2)));
+        std::vector<double> scl(kk);
+        for (int j = 0; j < kk; ++j) {
+            const double v = fg[(size_t)j * kk + j].x;
+            scl[j] = v > 0 ? 1.0 / std::sqrt(4.0 * v) : 0.0;
+        }
+        BDG_TRY(h2d(c, d_n, scl.data(), kk * sizeof(double)));
+        hipLaunchKernelGGL(k_make_uv, grid_cols(nh, kk), dim3(256), 0, c->stream, nh, kk, (const double2*)F,
+                           (const double2*)G, (const double*)d_n, (double2*)UV_dev);
+        BDG_HIP(c, hipGetLastError());
+    }
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    c->stats[0] = ms_since(t_start);
+    c->stats[1] = t_apply;
+    c->stats[2] = t_prec;
+    c->stats[3] = t_gram;
+    c->stats[4] = t_small;
+    c->stats[5] = t_upd;
+    c->stats[7] = std::min(it, max_iter);
+    c->stats[8] = napply64;
+    c->stats[9] = napply32;
+    // release
+    small_free(c, w);
+    for (int a = 0; a < 4; ++a) ctx_free(c, S.arr[a]);
+    ctx_free(c, w32);
+    ctx_free(c, y32);
+    ctx_free(c, acoef);
+    ctx_free(c, bcoef);
+    ctx_free(c, dvec);
+    ctx_free(c, D.Nm);
+    ctx_free(c, D.Qg);
+    if (final_status == BDG_ENOCONV) return ctx_fail(c, BDG_ENOCONV, "bdg_eigs: iteration limit reached");
+    return final_status;
+}
+
+}  // namespace
+
+extern "C" bdg_status bdg_eigs(bdg_ctx* c, int k, int block, double tol, int max_iter, const void* X0_dev,
+                               unsigned long long seed, double* omega, void* UV_dev, double* residual, int* iters) {
+    if (!c) return BDG_EINVAL;
+    if (k < 1 || block < k || block > 160 || (long long)block > 6 * c->npts)
+        return ctx_fail(c, BDG_EINVAL, "bdg_eigs: need 1 <= k <= block <= min(160, 6 npts)");
+    if (!(tol > 0) || max_iter < 1) return ctx_fail(c, BDG_EINVAL, "bdg_eigs: bad tol or max_iter");
+    if (!omega) return ctx_fail(c, BDG_EINVAL, "bdg_eigs: omega is null");
+    if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "bdg_eigs: no ground state set");
+    return eigs_impl(c, k, block, tol, max_iter, X0_dev, seed, omega, UV_dev, residual, iters);
+}

@@ -1,0 +1,87 @@
+"""Parity of the HIP BdG operator (bdg_apply) with the oracle's literal def_A/def_B operator."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bdg
+from tests.gpu_util import make_ctx, oracle_ground, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    W.C1,
+    W.Workload("2d_16x32_fm", 2, (16, 32), (6.0, 8.0), "harmonic2_aniso", 20.0, -1.0, 0.1),
+    W.Workload("2d_64_polar", 2, (64, 64), (8.0, 8.0), "harmonic2", 50.0, 1.0, 0.0),
+    W.Workload("3d_16x8x32_fm", 3, (16, 8, 32), (4.0, 3.0, 5.0), "harmonic3_z2", 10.0, -0.5, 0.2),
+    W.Workload("3d_32_afm", 3, (32, 32, 32), (5.0, 5.0, 5.0), "harmonic3", 30.0, 1.5, 0.3),
+    W.Workload("1d_512_fm", 1, (512,), (16.0,), "harmonic1", 10.0, -0.5, 0.2),
+    W.Workload("2d_8x256_fm", 2, (8, 256), (3.0, 12.0), "harmonic2", 10.0, -0.5, 0.0),
+]
+
+
+@pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
+@pytest.mark.parametrize("form", ["fg", "uv"])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_apply_fp64_matches_oracle(w, form, transpose):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Form, Precision
+    say(f"apply fp64 {w.name} {form} T={transpose}")
+    V, r, coef = oracle_ground(w)
+    ctx = make_ctx(w, Precision.FP64, V)
+    ctx.set_ground_state(torch.from_numpy(r.phi), r.mu)
+    X = W.random_block((3, 6) + w.shape, seed=7, smooth=0.0)
+    Xd = torch.from_numpy(X).to("cuda")
+    Y = ctx.apply(Xd, Form.FG if form == "fg" else Form.UV, bool(transpose)).cpu().numpy()
+    if form == "fg":
+        ref = bdg.apply_fg(coef, X, w.n, w.L)
+        if transpose:   # adjoint: (H_+ g, H_- f)
+            Hp, Hm = bdg.hpm(coef)
+            from oracle import spectral
+            f, g = X[:, :3], X[:, 3:]
+            ref = np.concatenate([spectral.kinetic_apply(g, w.n, w.L) + bdg._pw(Hp, g),
+                                  spectral.kinetic_apply(f, w.n, w.L) + bdg._pw(Hm, f)], axis=1)
+    else:
+        if transpose:   # [[A, B], [C, D]]^T with the oracle blocks: [[A^T, C^T], [B^T, D^T]]
+            tr = lambda M: np.swapaxes(M, 0, 1)
+            c2 = bdg.Coefficients(A=tr(coef.A), B=tr(coef.C), C=tr(coef.B), D=tr(coef.D))
+            ref = bdg.apply_uv(c2, X, w.n, w.L)
+        else:
+            ref = bdg.apply_uv(coef, X, w.n, w.L)
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("w", CASES[:5], ids=lambda w: w.name)
+def test_apply_fp32_matches_oracle(w):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Form, Precision
+    say(f"apply fp32 {w.name}")
+    V, r, coef = oracle_ground(w)
+    ctx = make_ctx(w, Precision.FP32_APPLY, V)
+    ctx.set_ground_state(torch.from_numpy(r.phi), r.mu)
+    X = W.random_block((2, 6) + w.shape, seed=8)
+    X32 = X.astype(np.complex64)
+    Y = ctx.apply(torch.from_numpy(X32).to("cuda"), Form.FG).cpu().numpy().astype(np.complex128)
+    ref = bdg.apply_fg(coef, X32.astype(np.complex128), w.n, w.L)
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 2e-6
+    ctx.close()
+
+
+def test_apply_rejects_bad_arguments():
+    torch = torch_cuda()
+    from paper_2506_08308_amd import BdgError, Form, Precision
+    w = CASES[1]
+    V, r, coef = oracle_ground(w)
+    ctx = make_ctx(w, Precision.FP64, V)
+    X = torch.zeros((1, 6) + w.shape, dtype=torch.complex128, device="cuda")
+    with pytest.raises(BdgError) as e:           # no ground state yet
+        ctx.apply(X, Form.FG)
+    assert "BDG_ESTATE" in str(e.value)
+    ctx.set_ground_state(torch.from_numpy(r.phi), r.mu)
+    with pytest.raises(BdgError):                # X and Y overlap
+        ctx.apply(X, Form.FG, out=X)
+    ctx.close()

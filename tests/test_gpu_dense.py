@@ -1,0 +1,109 @@
+"""Parity of the dense kernels (MFMA Gram and update, Jacobi SVD, Cholesky) with numpy."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import make_ctx, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+W2 = W.Workload("2d_8", 2, (8, 8), (2.0, 2.0), "harmonic2", 1.0, -0.1, 0.0)
+
+
+def _ctx():
+    from paper_2506_08308_amd import Precision
+    return make_ctx(W2, Precision.FP64)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@pytest.mark.parametrize("K,m1,m2,herm", [(37, 5, 7, 0), (1000, 40, 40, 0), (3072, 64, 64, 1), (5000, 80, 120, 0),
+                                          (100000, 240, 240, 1), (70001, 16, 3, 0), (12, 130, 130, 1)])
+def test_gram_matches_numpy(K, m1, m2, herm):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"gram K={K} {m1}x{m2} herm={herm}")
+    ctx = _ctx()
+    A = W.random_block((m1, K), seed=1)
+    B = A if herm else W.random_block((m2, K), seed=2)
+    Ad = torch.from_numpy(A).cuda()
+    Bd = Ad if herm else torch.from_numpy(B).cuda()
+    C = torch.zeros((m2, m1), dtype=torch.complex128, device="cuda")   # column-major m1 x m2
+    st = ctx._lib.bdg_test_gram(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 0.5, _p(C), m1, herm)
+    assert st == _lib.BDG_OK
+    got = C.cpu().numpy().T
+    ref = 0.5 * (A.conj() @ B.T)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("K,m,nb,beta", [(37, 5, 3, 0.0), (1000, 40, 16, 0.0), (5000, 240, 80, 1.0),
+                                         (129, 7, 33, -0.5), (100000, 24, 8, 0.0)])
+def test_update_matches_numpy(K, m, nb, beta):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"update K={K} m={m} nb={nb}")
+    ctx = _ctx()
+    S = W.random_block((m, K), seed=3)
+    Cm = W.random_block((nb, m), seed=4)      # column-major m x nb
+    Y0 = W.random_block((nb, K), seed=5)
+    Sd, Cd, Yd = (torch.from_numpy(a).cuda() for a in (S, Cm, Y0))
+    st = ctx._lib.bdg_test_update(ctx._h, K, m, _p(Sd), K, _p(Cd), m, nb, beta, _p(Yd), K)
+    assert st == _lib.BDG_OK
+    got = Yd.cpu().numpy()
+    ref = (S.T @ Cm.T).T + beta * Y0
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("rows,m", [(6, 6), (40, 40), (37, 24), (240, 240), (17, 33)])
+def test_jacobi_svd_matches_numpy(rows, m):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"svd {rows}x{m}")
+    ctx = _ctx()
+    G = W.random_block((m, rows), seed=6)     # column-major rows x m
+    Gd = torch.from_numpy(G.copy()).cuda()
+    V = torch.zeros((m, m), dtype=torch.complex128, device="cuda")
+    s = torch.zeros(m, dtype=torch.float64, device="cuda")
+    st = ctx._lib.bdg_test_svd(ctx._h, rows, m, _p(Gd), rows, _p(V), m, _p(s))
+    assert st == _lib.BDG_OK
+    Gm = G.T                                   # rows x m
+    s_ref = np.linalg.svd(Gm, compute_uv=False)
+    sh = s.cpu().numpy()
+    kk = min(rows, m)
+    assert np.allclose(sh[:kk], s_ref[:kk], rtol=1e-12, atol=1e-12 * s_ref[0])
+    assert np.all(sh[kk:] < 1e-12 * s_ref[0])
+    Vm = V.cpu().numpy().T
+    US = Gd.cpu().numpy().T
+    assert np.abs(Gm @ Vm - US).max() < 1e-12 * s_ref[0]
+    assert np.abs(Vm.conj().T @ Vm - np.eye(m)).max() < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("m", [1, 5, 64, 240])
+def test_cholesky_matches_numpy(m):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"cholesky {m}")
+    ctx = _ctx()
+    X = W.random_block((m, m), seed=7)
+    A = X @ X.conj().T + m * np.eye(m)
+    Ad = torch.from_numpy(A.T.copy()).cuda()   # column-major
+    st = ctx._lib.bdg_test_cholesky(ctx._h, m, _p(Ad), m)
+    assert st == _lib.BDG_OK
+    Lg = Ad.cpu().numpy().T
+    assert np.allclose(Lg, np.linalg.cholesky(A), rtol=1e-12, atol=1e-12 * np.sqrt(m))
+    # an indefinite matrix is reported
+    B = -np.eye(m)
+    Bd = torch.from_numpy(B.astype(np.complex128)).cuda()
+    assert ctx._lib.bdg_test_cholesky(ctx._h, m, _p(Bd), m) == _lib.BDG_EBREAKDOWN
+    ctx.close()
