@@ -33,6 +33,16 @@ bdg_status bdg_test_svd(bdg_ctx* ctx, int rows, int m, void* G, int ldg, void* V
  * returns BDG_EBREAKDOWN when a pivot is not positive. */
 bdg_status bdg_test_cholesky(bdg_ctx* ctx, int m, void* A, int lda);
 
+/* Pivoted Cholesky orthonormalization of a Hermitian PSD Gram matrix A (m x m, destroyed):
+ * R (m x m, ldr = m) receives r columns with R^H A R = I; *rank (host) = r.  Columns are
+ * scaled to unit diagonal first; the factorization stops when the largest remaining Schur
+ * diagonal is <= rtol. */
+bdg_status bdg_test_pchol(bdg_ctx* ctx, int m, void* A, int lda, double rtol, void* R, int* rank);
+
+/* LU with complete pivoting of B (p x q, destroyed), stopping at |pivot| <= tol:
+ * Cf (q x r, ld q) and Cg (p x r, ld p) with Cg^H B Cf = I_r; *rank (host) = r. */
+bdg_status bdg_test_plu(bdg_ctx* ctx, int p, int q, void* B, int ldb, double tol, void* Cf, void* Cg, int* rank);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,8 @@ BDG_FORM_UV, BDG_FORM_FG = 0, 1
 
 EXPORTS = ("bdg_create", "bdg_destroy", "bdg_last_error", "bdg_ground_state", "bdg_set_ground_state",
            "bdg_apply", "bdg_biortho", "bdg_eigs", "bdg_eigs_grad", "bdg_stats",
-           "bdg_test_gram", "bdg_test_update", "bdg_test_svd", "bdg_test_cholesky")
+           "bdg_test_gram", "bdg_test_update", "bdg_test_svd", "bdg_test_cholesky", "bdg_test_pchol",
+           "bdg_test_plu")
 
 
 class Problem(ctypes.Structure):
@@ -65,5 +66,9 @@ def load() -> ctypes.CDLL:
     lib.bdg_test_svd.restype = st
     lib.bdg_test_cholesky.argtypes = [vp, i, vp, i]
     lib.bdg_test_cholesky.restype = st
+    lib.bdg_test_pchol.argtypes = [vp, i, vp, i, d, vp, pi]
+    lib.bdg_test_pchol.restype = st
+    lib.bdg_test_plu.argtypes = [vp, i, i, vp, i, d, vp, vp, pi]
+    lib.bdg_test_plu.restype = st
     _lib = lib
     return lib

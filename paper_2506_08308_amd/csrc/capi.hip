@@ -331,4 +331,25 @@ bdg_status bdg_test_cholesky(bdg_ctx* c, int m, void* A, int lda) {
     return h ? ctx_fail(c, BDG_EBREAKDOWN, "not positive definite") : BDG_OK;
 }
 
+bdg_status bdg_test_pchol(bdg_ctx* c, int m, void* A, int lda, double rtol, void* R, int* rank) {
+    if (!c || !A || !R || !rank || m < 1 || m > 512 || lda < m) return ctx_fail(c, BDG_EINVAL, "bad args");
+    int* d = nullptr;
+    BDG_TRY(ctx_alloc(c, (void**)&d, sizeof(int)));
+    bdg_status st = small_pchol_orth(c, m, (double2*)A, lda, rtol, (double2*)R, d);
+    if (st == BDG_OK && hipMemcpy(rank, d, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) st = BDG_EDEVICE;
+    ctx_free(c, d);
+    return st;
+}
+
+bdg_status bdg_test_plu(bdg_ctx* c, int p, int q, void* B, int ldb, double tol, void* Cf, void* Cg, int* rank) {
+    if (!c || !B || !Cf || !Cg || !rank || p < 1 || q < 1 || p > 512 || q > 512 || ldb < p)
+        return ctx_fail(c, BDG_EINVAL, "bad args");
+    int* d = nullptr;
+    BDG_TRY(ctx_alloc(c, (void**)&d, sizeof(int)));
+    bdg_status st = small_plu_biorth(c, p, q, (double2*)B, ldb, tol, (double2*)Cf, (double2*)Cg, d);
+    if (st == BDG_OK && hipMemcpy(rank, d, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) st = BDG_EDEVICE;
+    ctx_free(c, d);
+    return st;
+}
+
 }  // extern "C"

@@ -152,6 +152,14 @@ bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev)
 // V (m x m) receives V, s (m, device) the column norms; columns sorted by descending s.
 bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s);
 
+// pivoted Cholesky of a Gram matrix A (m x m, destroyed; diagonally scaled inside):
+// R (m x m, ld m) gets r columns with R^H A R = I; *rank_dev = r (Schur diagonal cut rtol)
+bdg_status small_pchol_orth(bdg_ctx* c, int m, double2* A, int lda, double rtol, double2* R, int* rank_dev);
+// LU with complete pivoting of B (p x q, destroyed): Cf (q x r, ld q), Cg (p x r, ld p) with
+// Cg^H B Cf = I_r; *rank_dev = r (pivot cut tol)
+bdg_status small_plu_biorth(bdg_ctx* c, int p, int q, double2* B, int ldb, double tol, double2* Cf, double2* Cg,
+                            int* rank_dev);
+
 // column norms squared (deterministic), etc.
 bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx,
                     double* out_dev);

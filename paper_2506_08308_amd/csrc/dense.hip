@@ -294,98 +294,145 @@ __global__ void __launch_bounds__(1024) k_small_cholesky(int m, double2* A, int 
     if (t == 0) *info = bad;
 }
 
-// One-sided Jacobi SVD (round-robin ordering, complex rotations) in one workgroup.
-// G (rows x m) -> G V; V (m x m) accumulates the rotations (starts as identity).
-__global__ void __launch_bounds__(1024) k_small_jacobi(int rows, int m, double2* G, int ldg, double2* V, int ldv,
-                                                      int tpp, int max_sweeps) {
-    __shared__ int rotated;
-    __shared__ double fro[32];
-    const int t = threadIdx.x;
-    const int mm = (m + 1) & ~1;           // even number of players (one padding column)
-    const int npairs = mm / 2;
-    const int pair = t / tpp, sub = t % tpp;
+// One-sided Jacobi SVD by column blocks (round-robin ordering of blocks, complex rotations).
+// A launch processes one round: workgroup b takes a pair of blocks of w columns, stages their
+// columns of G (rows) and V (m) in LDS, runs one sweep over all pairs of its 2w columns and
+// writes them back.  Rotations of columns whose squared norm is below negl (1e-30 ||G||_F^2)
+// are skipped: such columns are numerically zero.
+__global__ void k_identity_frob(int rows, int m, const double2* __restrict__ G, int ldg, double2* V, int ldv,
+                                double* frob2, int* counter) {
+    __shared__ double red[16];
     double fs = 0;
-    for (long long e = t; e < (long long)m * m; e += blockDim.x) {
+    for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
         const int i = (int)(e % m), l = (int)(e / m);
         V[(long long)l * ldv + i] = mkc(i == l ? 1.0 : 0.0, 0.0);
     }
-    for (long long e = t; e < (long long)rows * m; e += blockDim.x) {
+    for (long long e = threadIdx.x; e < (long long)rows * m; e += blockDim.x) {
         const double2 g = G[(e / rows) * ldg + e % rows];
         fs += g.x * g.x + g.y * g.y;
     }
     for (int off = 32; off > 0; off >>= 1) fs += __shfl_down(fs, off);
-    if ((t & 63) == 0) fro[t >> 6] = fs;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fs;
     __syncthreads();
-    double frob2 = 0;
-    for (int wv = 0; wv < (int)((blockDim.x + 63) / 64); ++wv) frob2 += fro[wv];
-    // columns below 1e-15 ||G||_F are numerically zero: no rotation against them
-    const double negl = 1e-30 * frob2;
-    const double tol = 1e-15;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (t == 0) rotated = 0;
-        __syncthreads();
-        for (int rnd = 0; rnd < mm - 1; ++rnd) {
-            int pcol = -1, qcol = -1;
-            if (pair < npairs) {
-                auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (mm - 1)) + 1; };
-                pcol = player(pair);
-                qcol = player(mm - 1 - pair);
-                if (pcol > qcol) { int tmp = pcol; pcol = qcol; qcol = tmp; }
-                if (qcol >= m) pcol = -1;      // padding player
-            }
-            double al = 0, be = 0, gx = 0, gy = 0;
-            if (pcol >= 0) {
-                const double2* gp = G + (long long)pcol * ldg;
-                const double2* gq = G + (long long)qcol * ldg;
-                for (int i = sub; i < rows; i += tpp) {
-                    double2 a = gp[i], b = gq[i];
-                    al += a.x * a.x + a.y * a.y;
-                    be += b.x * b.x + b.y * b.y;
-                    gx += a.x * b.x + a.y * b.y;     // conj(a) b
-                    gy += a.x * b.y - a.y * b.x;
-                }
-            }
-            for (int off = 1; off < tpp; off <<= 1) {
-                al += __shfl_xor(al, off);
-                be += __shfl_xor(be, off);
-                gx += __shfl_xor(gx, off);
-                gy += __shfl_xor(gy, off);
-            }
-            if (pcol >= 0) {
-                const double g = sqrt(gx * gx + gy * gy);
-                if (g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
-                    if (sub == 0) rotated = 1;
-                    const double zeta = (be - al) / (2.0 * g);
-                    const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
-                                                         : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-                    // e^{-i theta} with gamma = |gamma| e^{i theta}
-                    const double ex = gx / g, ey = -gy / g;
-                    // [p', q'] = [c p - s e q, s p + c e q]
-                    double2* gp = G + (long long)pcol * ldg;
-                    double2* gq = G + (long long)qcol * ldg;
-                    for (int i = sub; i < rows; i += tpp) {
-                        double2 a = gp[i], b = gq[i];
-                        double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
-                        gp[i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                        gq[i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
-                    }
-                    double2* vp = V + (long long)pcol * ldv;
-                    double2* vq = V + (long long)qcol * ldv;
-                    for (int i = sub; i < m; i += tpp) {
-                        double2 a = vp[i], b = vq[i];
-                        double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
-                        vp[i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                        vq[i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+    if (threadIdx.x == 0) {
+        double a = 0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) a += red[w];
+        *frob2 = a;
+        *counter = 0;
+    }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+__global__ void __launch_bounds__(256) k_bjacobi_round(int rows, int m, double2* G, int ldg, double2* V, int ldv,
+                                                       int w, int nblk, int rnd, const double* __restrict__ frob2,
+                                                       int* rotations) {
+    extern __shared__ double2 sm[];
+    __shared__ int rot_any;
+    const int t = threadIdx.x;
+    auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (nblk - 1)) + 1; };
+    const int P = player(blockIdx.x), Q = player(nblk - 1 - blockIdx.x);
+    const int c0[2] = {P * w, Q * w};
+    int nc[2];
+    for (int h = 0; h < 2; ++h) {
+        const int lim = m - c0[h];
+        nc[h] = lim <= 0 ? 0 : (lim < w ? lim : w);
+    }
+    double2* lg = sm;                          // 2w columns of G, pitch rows
+    double2* lv = sm + (size_t)2 * w * rows;   // 2w columns of V, pitch m
+    if (t == 0) rot_any = 0;
+    // stage (flattened, eight independent loads in flight per thread)
+    {
+        const int ng = 2 * w * rows, nv = 2 * w * m, tot = ng + nv;
+        for (int e0 = t; e0 < tot; e0 += 8 * blockDim.x) {
+            double2 buf[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * blockDim.x;
+                buf[u] = mkc(0.0, 0.0);
+                if (e < tot) {
+                    const bool isg = e < ng;
+                    const int ee = isg ? e : e - ng, len = isg ? rows : m;
+                    const int cidx = ee / len, i = ee % len, h = cidx / w, cc = cidx % w;
+                    if (cc < nc[h]) {
+                        const long long col = c0[h] + cc;
+                        buf[u] = isg ? G[col * ldg + i] : V[col * ldv + i];
                     }
                 }
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * blockDim.x;
+                if (e < tot) sm[e] = buf[u];
+            }
+        }
+    }
+    __syncthreads();
+    const double negl = 1e-30 * (*frob2);
+    const double tol = 1e-15, conv = 1e-13;
+    const int tpp = blockDim.x / w;            // threads per column pair (w pairs per inner round)
+    const int pair = t / tpp, sub = t % tpp;
+    const int n2 = 2 * w;
+    for (int r2 = 0; r2 < n2 - 1; ++r2) {
+        auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (n2 - 1)) + 1; };
+        int p = pl(pair), q = pl(n2 - 1 - pair);
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        const bool valid = (p % w) < nc[p / w] && (q % w) < nc[q / w];
+        double al = 0, be = 0, gx = 0, gy = 0;
+        if (valid) {
+            for (int i = sub; i < rows; i += tpp) {
+                const double2 a = lg[p * rows + i], b = lg[q * rows + i];
+                al += a.x * a.x + a.y * a.y;
+                be += b.x * b.x + b.y * b.y;
+                gx += a.x * b.x + a.y * b.y;
+                gy += a.x * b.y - a.y * b.x;
+            }
+        }
+        for (int off = 1; off < tpp; off <<= 1) {
+            al += __shfl_xor(al, off);
+            be += __shfl_xor(be, off);
+            gx += __shfl_xor(gx, off);
+            gy += __shfl_xor(gy, off);
+        }
+        const double g = sqrt(gx * gx + gy * gy);
+        if (valid && g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
+            // a sweep counts as converged once every pair is below conv (quadratic convergence:
+            // one more sweep would take the off-diagonal to ~conv^2)
+            if (sub == 0 && g > conv * sqrt(al * be)) rot_any = 1;
+            const double zeta = (be - al) / (2.0 * g);
+            const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
+                                                 : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+            const double ex = gx / g, ey = -gy / g;     // e^{-i theta}, gamma = |gamma| e^{i theta}
+            for (int i = sub; i < rows; i += tpp) {
+                const double2 a = lg[p * rows + i], b = lg[q * rows + i];
+                const double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
+                lg[p * rows + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                lg[q * rows + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+            }
+            for (int i = sub; i < m; i += tpp) {
+                const double2 a = lv[p * m + i], b = lv[q * m + i];
+                const double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
+                lv[p * m + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                lv[q * m + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+            }
         }
         __syncthreads();
-        if (!rotated) break;
-        __syncthreads();
     }
+    // write back
+    {
+        const int ng = 2 * w * rows, nv = 2 * w * m, tot = ng + nv;
+        for (int e = t; e < tot; e += blockDim.x) {
+            const bool isg = e < ng;
+            const int ee = isg ? e : e - ng, len = isg ? rows : m;
+            const int cidx = ee / len, i = ee % len, h = cidx / w, cc = cidx % w;
+            if (cc >= nc[h]) continue;
+            const long long col = c0[h] + cc;
+            if (isg) G[col * ldg + i] = sm[e];
+            else V[col * ldv + i] = sm[e];
+        }
+    }
+    if (t == 0 && rot_any) atomicAdd(rotations, 1);
 }
 
 // column norms of G (rows x m) into s; permutation to descending order (stable), applied to
@@ -556,13 +603,42 @@ bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev)
 
 bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s) {
     if (m <= 0) return BDG_OK;
-    if (m > 512 || rows > 4096) return ctx_fail(c, BDG_EINVAL, "small_svd: size out of range");
-    const int npairs = ((m + 1) & ~1) / 2;
-    int tpp = 64;
-    while (tpp > 1 && npairs * tpp > 1024) tpp >>= 1;
-    const int threads = ((npairs * tpp + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_small_jacobi, dim3(1), dim3(threads), 0, c->stream, rows, m, G, ldg, V, ldv, tpp, 60);
+    if (m > 512 || rows > 512) return ctx_fail(c, BDG_EINVAL, "small_svd: size out of range");
+    // block width: both blocks of G (rows) and V (m) must fit in the workgroup's LDS
+    static int lds_limit = 0;
+    if (lds_limit == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        lds_limit = v;
+    }
+    int w = 16;
+    while (w > 4 && (size_t)2 * w * (rows + m) * sizeof(double2) + 64 > (size_t)lds_limit) w >>= 1;
+    if ((size_t)2 * w * (rows + m) * sizeof(double2) + 64 > (size_t)lds_limit)
+        return ctx_fail(c, BDG_EINVAL, "small_svd: matrix too large for the LDS-staged Jacobi");
+    int nblk = (m + w - 1) / w;
+    if (nblk < 2) nblk = 2;
+    if (nblk & 1) ++nblk;
+    void* aux = nullptr;
+    BDG_TRY(ctx_scratch(c, 3, 64, &aux));
+    double* frob2 = (double*)aux;
+    int* counter = (int*)((char*)aux + 16);
+    hipLaunchKernelGGL(k_identity_frob, dim3(1), dim3(1024), 0, c->stream, rows, m, (const double2*)G, ldg, V, ldv,
+                       frob2, counter);
     BDG_HIP(c, hipGetLastError());
+    const size_t lds = (size_t)2 * w * (rows + m) * sizeof(double2);
+    BDG_HIP(c, hipFuncSetAttribute((const void*)k_bjacobi_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, counter);
+        for (int rnd = 0; rnd < nblk - 1; ++rnd)
+            hipLaunchKernelGGL(k_bjacobi_round, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V, ldv, w,
+                               nblk, rnd, (const double*)frob2, counter);
+        BDG_HIP(c, hipGetLastError());
+        int h = 0;
+        BDG_HIP(c, hipMemcpyAsync(&h, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        BDG_HIP(c, hipStreamSynchronize(c->stream));
+        if (h == 0) break;
+    }
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 1, ((size_t)rows * m + (size_t)m * m) * sizeof(double2), &ws));
     hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, c->stream, rows, m, G, ldg, V, ldv, s, (double2*)ws,

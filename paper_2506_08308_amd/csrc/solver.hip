@@ -154,42 +154,6 @@ __global__ void k_small_gather(int rows, int nsel, const double2* __restrict__ A
     }
 }
 
-// dinv_i = 1/sqrt(A_ii), A_ij *= dinv_i dinv_j (symmetric diagonal scaling).  Columns whose
-// squared norm is below 1e-20 of the largest count as zero (dinv_i = 0), so that the rank
-// detection that follows still sees them as dependent.
-__global__ void k_small_diagscale(int m, double2* A, int lda, double* __restrict__ dinv) {
-    __shared__ double ds[512];
-    __shared__ double dmax;
-    if (threadIdx.x == 0) {
-        double mx = 0;
-        for (int i = 0; i < m; ++i) mx = fmax(mx, A[(long long)i * lda + i].x);
-        dmax = mx;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const double d = A[(long long)i * lda + i].x;
-        ds[i] = (d > 1e-20 * dmax && d > 0) ? 1.0 / sqrt(d) : 0.0;
-        dinv[i] = ds[i];
-    }
-    __syncthreads();
-    for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
-        const int i = (int)(e % m), j = (int)(e / m);
-        double2 a = A[(long long)j * lda + i];
-        const double f = ds[i] * ds[j];
-        A[(long long)j * lda + i] = cmk<double2>(a.x * f, a.y * f);
-    }
-}
-
-// A(i, :) *= d_i
-__global__ void k_small_rowscale(int rows, int cols, double2* A, int lda, const double* __restrict__ d) {
-    const int j = blockIdx.x;
-    if (j >= cols) return;
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
-        double2 a = A[(long long)j * lda + i];
-        A[(long long)j * lda + i] = cmk<double2>(a.x * d[i], a.y * d[i]);
-    }
-}
-
 __global__ void k_small_herm(int m, double2* A, int lda) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
     if (i >= m || j >= m || i > j) return;
@@ -279,28 +243,6 @@ bdg_status small_colpow(bdg_ctx* c, int rows, int cols, double2* A, int lda, con
     return hip_check(c, hipGetLastError(), "k_small_colpow");
 }
 
-// R (m x r) with S R orthonormal, from the Hermitian PSD Gram matrix Gm (m x m): the
-// Gram matrix is first scaled to unit diagonal (columns of very different norms would
-// otherwise hide small independent components), then G~ = V diag(l) V^H (Jacobi) and
-// R = D^-1/2 V diag(l)^-1/2 over the eigenvalues l > rtol * max(l).
-bdg_status orth_factor(bdg_ctx* c, Small& w, int m, const double2* Gm, double2* T, double2* R, double* s, double rtol,
-                       int* r_out) {
-    BDG_TRY(small_copy(c, m, m, Gm, m, T, m));
-    double* dinv = w.dscale + w.cap;          // second half of the scale buffer
-    hipLaunchKernelGGL(k_small_diagscale, dim3(1), dim3(1024), 0, c->stream, m, T, m, dinv);
-    BDG_HIP(c, hipGetLastError());
-    BDG_TRY(small_svd(c, m, m, T, m, R, m, s));
-    std::vector<double> hs(m);
-    BDG_TRY(d2h(c, hs.data(), s, m * sizeof(double)));
-    int r = 0;
-    while (r < m && hs[r] > rtol * hs[0] && hs[r] > 0) ++r;
-    BDG_TRY(small_colpow(c, m, r, R, m, s, -0.5));
-    hipLaunchKernelGGL(k_small_rowscale, dim3((unsigned)r), dim3(256), 0, c->stream, m, r, R, m, (const double*)dinv);
-    BDG_HIP(c, hipGetLastError());
-    *r_out = r;
-    return BDG_OK;
-}
-
 // Projected problem (see file header).  Inputs m x m (ld m): Gf, Gg, Br, Mr, Kr.  Outputs
 // acoef, bcoef (m x nb, ld m) and omega (host, ascending).  Returns BDG_EBREAKDOWN when the
 // usable rank is below nb or a projected matrix is not numerically positive definite.
@@ -316,24 +258,26 @@ bdg_status rr_once(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const
     double2* Cg = w.buf[11];
     double2* X1 = w.buf[12];
     double2* X2 = w.buf[13];
-    int rf = 0, rg = 0;
-    BDG_TRY(orth_factor(c, w, m, Gf, T, Rf, w.s[0], rtol, &rf));
-    BDG_TRY(orth_factor(c, w, m, Gg, T, Rg, w.s[1], rtol, &rg));
+    // orthonormal bases of the two spaces (pivoted Cholesky of the scaled Gram matrices)
+    BDG_TRY(small_copy(c, m, m, Gf, m, T, m));
+    BDG_TRY(small_pchol_orth(c, m, T, m, rtol, Rf, w.info + 2));
+    BDG_TRY(small_copy(c, m, m, Gg, m, T, m));
+    BDG_TRY(small_pchol_orth(c, m, T, m, rtol, Rg, w.info + 3));
+    int rk[2];
+    BDG_TRY(d2h(c, rk, w.info + 2, 2 * sizeof(int)));
+    const int rf = rk[0], rg = rk[1];
     if (rf < nb || rg < nb) return ctx_fail(c, BDG_EBREAKDOWN, "basis rank below block size");
-    // B = Rg^H Br Rf (rg x rf)
+    // pairing matrix of the orthonormal bases B = Rg^H Br Rf (rg x rf), bi-orthogonalized by
+    // LU with complete pivoting: Cg'^H B Cf' = I_r
     BDG_TRY(small_gemm(c, 0, 0, m, rf, m, ONE, Br, m, Rf, m, ZERO, T, m));
     BDG_TRY(small_gemm(c, 1, 0, rg, rf, m, ONE, Rg, m, T, m, ZERO, B, m));
-    BDG_TRY(small_svd(c, rg, rf, B, m, V3, m, w.s[2]));
-    std::vector<double> s3(rf);
-    BDG_TRY(d2h(c, s3.data(), w.s[2], rf * sizeof(double)));
+    BDG_TRY(small_plu_biorth(c, rg, rf, B, m, eps, X1, X2, w.info + 2));
     int r = 0;
-    while (r < rf && r < rg && s3[r] > eps) ++r;
+    BDG_TRY(d2h(c, &r, w.info + 2, sizeof(int)));
     if (r < nb) return ctx_fail(c, BDG_EBREAKDOWN, "bi-orthogonal rank below block size");
-    // Cf = Rf V3(:, :r) s^-1/2 ; Cg = Rg (U s)(:, :r) s^-3/2
-    BDG_TRY(small_gemm(c, 0, 0, m, r, rf, ONE, Rf, m, V3, m, ZERO, Cf, m));
-    BDG_TRY(small_colpow(c, m, r, Cf, m, w.s[2], -0.5));
-    BDG_TRY(small_gemm(c, 0, 0, m, r, rg, ONE, Rg, m, B, m, ZERO, Cg, m));
-    BDG_TRY(small_colpow(c, m, r, Cg, m, w.s[2], -1.5));
+    // Cf = Rf Cf' (m x r), Cg = Rg Cg' (m x r)
+    BDG_TRY(small_gemm(c, 0, 0, m, r, rf, ONE, Rf, m, X1, rf, ZERO, Cf, m));
+    BDG_TRY(small_gemm(c, 0, 0, m, r, rg, ONE, Rg, m, X2, rg, ZERO, Cg, m));
     // Mt = Cf^H Mr Cf -> X1 ; Kt = Cg^H Kr Cg -> X2
     BDG_TRY(small_gemm(c, 0, 0, m, r, m, ONE, Mr, m, Cf, m, ZERO, T, m));
     BDG_TRY(small_gemm(c, 1, 0, r, r, m, ONE, Cf, m, T, m, ZERO, X1, m));
@@ -350,8 +294,8 @@ bdg_status rr_once(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const
     std::vector<double> s4(r);
     BDG_TRY(d2h(c, info, w.info, 2 * sizeof(int)));
     if (debug_on())
-        fprintf(stderr, "[bdg rr] m=%d rf=%d rg=%d r=%d cos[min]=%.3e cos[r-1]=%.3e chol=(%d,%d) rtol=%.1e eps=%.1e\n", m,
-                rf, rg, r, s3[std::min(rf, rg) - 1], s3[r - 1], info[0], info[1], rtol, eps);
+        fprintf(stderr, "[bdg rr] m=%d rf=%d rg=%d r=%d chol=(%d,%d) rtol=%.1e eps=%.1e\n", m, rf, rg, r, info[0],
+                info[1], rtol, eps);
     if (info[0] || info[1]) return ctx_fail(c, BDG_EBREAKDOWN, "projected matrix not positive definite");
     BDG_TRY(d2h(c, s4.data(), w.s[3], r * sizeof(double)));
     // the nb smallest singular values, ascending
@@ -445,7 +389,8 @@ bdg_status orthonormalize(bdg_ctx* c, Small& w, long long nh, const double2* X, 
     if (p == 0) return BDG_OK;
     BDG_TRY(gram<double2, double2>(c, nh, p, p, X, nh, X, nh, c->hd, w.buf[0], p, 1));
     int r = 0;
-    BDG_TRY(orth_factor(c, w, p, w.buf[0], w.buf[1], w.buf[2], w.s[0], rtol, &r));
+    BDG_TRY(small_pchol_orth(c, p, w.buf[0], p, rtol, w.buf[2], w.info + 2));
+    BDG_TRY(d2h(c, &r, w.info + 2, sizeof(int)));
     Seg s{X, p};
     BDG_TRY(update(c, nh, &s, 1, nh, w.buf[2], p, r, 0.0, Out, nh));
     *r_out = r;
@@ -630,15 +575,15 @@ namespace {
 
 struct EigsOpts {
     double shift = 20.0;        // preconditioner shift sigma
-    double rtol = 1e-13;        // rank cut-off of the per-basis Gram eigenvalues
-    double eps = 1e-10;         // cut-off of the pairing cosines
+    double rtol = 1e-12;        // pivoted-Cholesky cut-off (Schur complement of the scaled Gram)
+    double eps = 1e-10;         // LU pivot cut-off of the pairing matrix
     double null_tol = 1e-6;     // nullspace candidate test
     double refresh_tol = 1e-5;  // mixed precision: refresh images once this residual is reached
     int refresh_every = 25;     // float64 re-projection and image refresh period (iterations)
     int stall_iters = 30;       // mixed form: switch to float64 applies after this many
                                 // iterations without halving the residual
     double rtol32 = 1e-10;      // cut-offs while images carry float32 rounding
-    double eps32 = 1e-7;
+    double eps32 = 1e-8;
 };
 
 bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const void* X0_dev,

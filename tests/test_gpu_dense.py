@@ -107,3 +107,48 @@ def test_cholesky_matches_numpy(m):
     Bd = torch.from_numpy(B.astype(np.complex128)).cuda()
     assert ctx._lib.bdg_test_cholesky(ctx._h, m, _p(Bd), m) == _lib.BDG_EBREAKDOWN
     ctx.close()
+
+
+@pytest.mark.parametrize("m,rank", [(12, 12), (48, 40), (144, 144), (240, 200)])
+def test_pivoted_cholesky_orthonormalizes(m, rank):
+    """R^H A R = I on the numerical range; dependent columns are detected."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"pchol m={m} rank={rank}")
+    ctx = _ctx()
+    K = 3 * m
+    S = W.random_block((rank, K), seed=9).T @ W.random_block((rank, m), seed=10)   # K x m, rank `rank`
+    S = S * np.exp(np.linspace(-3, 3, m))[None, :]                                  # uneven column norms
+    A = S.conj().T @ S
+    Ad = torch.from_numpy(A.T.copy()).cuda()
+    R = torch.zeros((m, m), dtype=torch.complex128, device="cuda")
+    r = ctypes.c_int()
+    st = ctx._lib.bdg_test_pchol(ctx._h, m, _p(Ad), m, 1e-12, _p(R), ctypes.byref(r))
+    assert st == _lib.BDG_OK and r.value == rank
+    Rm = R.cpu().numpy().T[:, :rank]
+    Q = S @ Rm
+    assert np.abs(Q.conj().T @ Q - np.eye(rank)).max() < 1e-6
+    # the span of S is kept
+    U, s, _ = np.linalg.svd(S, full_matrices=False)
+    U = U[:, :rank]
+    assert np.abs(Q - U @ (U.conj().T @ Q)).max() < 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("p,q,rank", [(10, 10, 10), (40, 36, 36), (144, 144, 130)])
+def test_complete_pivoting_lu_biorthogonalizes(p, q, rank):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"plu {p}x{q} rank={rank}")
+    ctx = _ctx()
+    B = W.random_block((rank, p), seed=11).T @ W.random_block((rank, q), seed=12)   # p x q
+    Bd = torch.from_numpy(B.T.copy()).cuda()
+    Cf = torch.zeros((q, q), dtype=torch.complex128, device="cuda")
+    Cg = torch.zeros((p, p), dtype=torch.complex128, device="cuda")
+    r = ctypes.c_int()
+    st = ctx._lib.bdg_test_plu(ctx._h, p, q, _p(Bd), p, 1e-10, _p(Cf), _p(Cg), ctypes.byref(r))
+    assert st == _lib.BDG_OK and r.value == rank
+    cf = Cf.cpu().numpy().reshape(-1)[:q * rank].reshape(rank, q).T
+    cg = Cg.cpu().numpy().reshape(-1)[:p * rank].reshape(rank, p).T
+    assert np.abs(cg.conj().T @ B @ cf - np.eye(rank)).max() < 1e-8
+    ctx.close()
