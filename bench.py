@@ -5,9 +5,10 @@ apply, bi-orthogonal Gram-Schmidt, Rayleigh-Ritz, updates, float64 certification
 seed-0 complex-normal start block to residual <= tol for all k wanted pairs.  The ground
 state is computed on the GPU (bdg_ground_state) before the timed region.
 
-Prints one JSON line (rank 0).  Default workload: 3-D 128^3 box [-8,8]^3, V=(x^2+y^2+4z^2)/2,
-beta_n=400, beta_s=-4, M=0.1, k=64, block 80, float32 apply with float64 projections,
-tol 1e-8.
+Prints one JSON line (rank 0).  Default workload: 2-D 256^2 box [-12,12]^2, V=(x^2+y^2)/2,
+beta_n=100, beta_s=-2 (ferromagnetic), M=0, k=32, block 48, float64, residual 1e-8.
+--workload c3 runs the 3-D 128^3 float32-apply case (k=64, block 80), c3_fp64 its float64
+counterpart, c2_polar the beta_s=+2 run.
 """
 from __future__ import annotations
 
@@ -118,7 +119,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2_fm", choices=sorted(WORKLOADS))
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

@@ -23,7 +23,7 @@
  *   complex128 (double2) in BDG_FP64 mode; bdg_apply takes complex64 (float2) blocks
  *   when the context was created with BDG_FP32_APPLY.
  *
- * Inner product (Section 3.3): <a, b> = h_x h_y h_z sum_j a_j conj(b_j).
+ * Inner product (Section 2.1, discretized as in Section 3.4): <a, b> = h_x h_y h_z sum_j a_j conj(b_j).
  *
  * Errors: every call returns a bdg_status; nothing else crosses the ABI (no exceptions,
  * no aborts).  The message of the last failure is kept in the context and returned by
@@ -121,7 +121,7 @@ bdg_status bdg_biortho(bdg_ctx* ctx, int nvec, void* F_dev, void* G_dev, double*
  * block drawn from `seed`).  omega (host, k): ascending; UV_dev (device, k x 6 npts
  * complex128): eigenvectors in (u, v) form with int |u|^2 - |v|^2 = 1 (i.e. <f, g> = 1/4);
  * may be NULL.  residual (host, k), iters (host) may be NULL.  Needs k <= block <= 6 npts
- * and block <= 256.  BDG_ENOCONV after max_iter iterations (outputs hold the last
+ * and block <= 160.  BDG_ENOCONV after max_iter iterations (outputs hold the last
  * iterate). */
 bdg_status bdg_eigs(bdg_ctx* ctx, int k, int block, double tol, int max_iter,
                     const void* X0_dev, unsigned long long seed, double* omega, void* UV_dev,

@@ -70,7 +70,7 @@ def kinetic_matrix(n, L) -> np.ndarray:
 
 
 def inner(a: np.ndarray, b: np.ndarray, h) -> complex:
-    """Discrete inner product <a, b> = h^d sum a * conj(b) (Section 3.3 convention)."""
+    """Discrete inner product <a, b> = h^d sum a * conj(b) (inner product of Section 2.1 on the grid, as in Section 3.4)."""
     return complex(np.prod(h) * np.vdot(b, a))
 
 

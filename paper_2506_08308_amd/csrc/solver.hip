@@ -930,3 +930,286 @@ extern "C" bdg_status bdg_eigs(bdg_ctx* c, int k, int block, double tol, int max
     if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "bdg_eigs: no ground state set");
     return eigs_impl(c, k, block, tol, max_iter, X0_dev, seed, omega, UV_dev, residual, iters);
 }
+
+// =====================================================================================
+// bdg_eigs_grad: eigenvalue gradients (Hellmann-Feynman form plus the ground-state
+// sensitivity through the linearized Euler-Lagrange problem of Section 1)
+//
+// With the left eigenvector (g, f) of [[0, H_-], [H_+, 0]] (the matrix J H = diag(H_+, H_-)
+// is Hermitian), d omega = (<dH_+ f, f> + <dH_- g, g>) / (2 Re <f, g>).  H_+- depend on a
+// parameter theta explicitly (V, beta_n, beta_s) and through Phi and Lambda = mu + lambda S_z.
+// The real-direction linearization of H(Phi) Phi - Lambda Phi is H_+, so the ground-state
+// sensitivity solves the bordered system
+//   H_+ dPhi - dmu Phi - dlambda S_z Phi = -d_theta(H Phi),  <Phi, dPhi> = <S_z Phi, dPhi> = 0.
+// The implicit part of d omega is <q, dPhi> + a_mu dmu + a_lambda dlambda with
+//   q = s grad_Phi (f^H C_+(Phi) f + g^H C_-(Phi) g),  a_mu = -s (|f|^2 + |g|^2),
+//   a_lambda = -s (<S_z f, f> + <S_z g, g>),  s = 1 / (2 Re <f, g>),
+// and the adjoint y (H_+ y + e_1 Phi + e_2 S_z Phi = q, <Phi, y> = -a_mu,
+// <S_z Phi, y> = -a_lambda) turns it into -<y, d_theta(H Phi)>:
+//   d omega / d V(x) / h^d = s sum_c (|f_c|^2 + |g_c|^2)(x) - sum_c y_c(x) Phi_c(x),
+//   d omega / d beta_n = s (<(rho + 2 Phi Phi^T) f, f> + <rho g, g>) - <y, rho Phi>,
+//   d omega / d beta_s = s (<(S.s + 2 x x^T + 2 z z^T) f, f> + <(S.s + 2 k k^T) g, g>) - <y, (S.s) Phi>
+// with x = S_x Phi, z = S_z Phi, k = K Phi.
+// =====================================================================================
+namespace {
+
+constexpr int RB2 = 256;
+
+template <int NQ> __device__ void reduce_store(double (&v)[NQ], double* part) {
+    __shared__ double red[NQ][RB2 / 64];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = v[q];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+        double a = 0;
+        for (int w = 0; w < RB2 / 64; ++w) a += red[threadIdx.x][w];
+        part[threadIdx.x * gridDim.x + blockIdx.x] = a;
+    }
+}
+
+__global__ void k_sum_parts(int nq, int nblk, const double* __restrict__ part, double scale, double* out) {
+    const int q = threadIdx.x;
+    if (q >= nq) return;
+    double a = 0;
+    for (int b = 0; b < nblk; ++b) a += part[q * nblk + b];
+    out[q] = a * scale;
+}
+
+// per point: densities, q field (unscaled), and the sums
+//   0: Re<f,g>, 1: <(rho+2PP^T)f,f> + <rho g,g>, 2: beta_s explicit form, 3: |f|^2+|g|^2,
+//   4: <S_z f,f> + <S_z g,g>
+__global__ void __launch_bounds__(RB2) k_grad_fields(long long npts, const double* __restrict__ phi,
+                                                     const double2* __restrict__ uv, double bn, double bs,
+                                                     double* __restrict__ dens, double2* __restrict__ qout,
+                                                     double* part) {
+    const double r2 = 0.70710678118654752440;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x) {
+        const double P[3] = {phi[p], phi[npts + p], phi[2 * npts + p]};
+        double2 F[3], G[3];
+        for (int c = 0; c < 3; ++c) {
+            const double2 u = uv[c * npts + p], v = uv[(3 + c) * npts + p];
+            F[c] = cmk<double2>(0.5 * (u.x + v.x), 0.5 * (u.y + v.y));
+            G[c] = cmk<double2>(0.5 * (u.x - v.x), 0.5 * (u.y - v.y));
+        }
+        const double rho = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+        const double sx = 1.4142135623730950488 * P[1] * (P[0] + P[2]), sz = P[0] * P[0] - P[2] * P[2];
+        // real symmetric matrices applied to complex vectors
+        auto Sx = [&](const double2* a, double2* o) {
+            o[0] = cmk<double2>(r2 * a[1].x, r2 * a[1].y);
+            o[1] = cmk<double2>(r2 * (a[0].x + a[2].x), r2 * (a[0].y + a[2].y));
+            o[2] = cmk<double2>(r2 * a[1].x, r2 * a[1].y);
+        };
+        auto Sz = [&](const double2* a, double2* o) { o[0] = a[0]; o[1] = cmk<double2>(0, 0); o[2] = cmk<double2>(-a[2].x, -a[2].y); };
+        auto Kt = [&](const double2* a, double2* o) {   // K^T a, K = [[0,-1,0],[1,0,-1],[0,1,0]]/sqrt2
+            o[0] = cmk<double2>(r2 * a[1].x, r2 * a[1].y);
+            o[1] = cmk<double2>(r2 * (-a[0].x + a[2].x), r2 * (-a[0].y + a[2].y));
+            o[2] = cmk<double2>(-r2 * a[1].x, -r2 * a[1].y);
+        };
+        auto dotr = [&](const double* a, const double2* b) {   // a^T b (a real)
+            return cmk<double2>(a[0] * b[0].x + a[1] * b[1].x + a[2] * b[2].x, a[0] * b[0].y + a[1] * b[1].y + a[2] * b[2].y);
+        };
+        auto herm = [&](const double2* a, const double2* b) {   // a^H b, real part
+            return a[0].x * b[0].x + a[0].y * b[0].y + a[1].x * b[1].x + a[1].y * b[1].y + a[2].x * b[2].x + a[2].y * b[2].y;
+        };
+        double2 SxF[3], SzF[3], SxG[3], SzG[3], KtG[3];
+        Sx(F, SxF); Sz(F, SzF); Sx(G, SxG); Sz(G, SzG); Kt(G, KtG);
+        const double nF = herm(F, F), nG = herm(G, G);
+        const double2 pF = dotr(P, F), pxF = dotr(P, SxF), pzF = dotr(P, SzF), pkG = dotr(P, KtG);
+        const double fSxf = herm(F, SxF), fSzf = herm(F, SzF), gSxg = herm(G, SxG), gSzg = herm(G, SzG);
+        const double a2F = pF.x * pF.x + pF.y * pF.y, ax2 = pxF.x * pxF.x + pxF.y * pxF.y;
+        const double az2 = pzF.x * pzF.x + pzF.y * pzF.y, ak2 = pkG.x * pkG.x + pkG.y * pkG.y;
+        acc[0] += F[0].x * G[0].x + F[0].y * G[0].y + F[1].x * G[1].x + F[1].y * G[1].y + F[2].x * G[2].x + F[2].y * G[2].y;
+        acc[1] += rho * nF + 2.0 * a2F + rho * nG;
+        acc[2] += sx * fSxf + sz * fSzf + 2.0 * ax2 + 2.0 * az2 + sx * gSxg + sz * gSzg + 2.0 * ak2;
+        acc[3] += nF + nG;
+        acc[4] += fSzf + gSzg;
+        dens[p] = nF + nG;
+        // grad_Phi of F^H C_+ F + G^H C_- G (real 3-vector), Re(conj(s) v) = s.x v.x + s.y v.y
+        const double SxP[3] = {r2 * P[1], r2 * (P[0] + P[2]), r2 * P[1]};
+        const double SzP[3] = {P[0], 0.0, -P[2]};
+        for (int c = 0; c < 3; ++c) {
+            double gq = bn * (2.0 * P[c] * nF + 4.0 * (pF.x * F[c].x + pF.y * F[c].y))
+                      + bs * (2.0 * fSxf * SxP[c] + 2.0 * fSzf * SzP[c] + 4.0 * (pxF.x * SxF[c].x + pxF.y * SxF[c].y)
+                              + 4.0 * (pzF.x * SzF[c].x + pzF.y * SzF[c].y))
+                      + bn * 2.0 * P[c] * nG
+                      + bs * (2.0 * gSxg * SxP[c] + 2.0 * gSzg * SzP[c] + 4.0 * (pkG.x * KtG[c].x + pkG.y * KtG[c].y));
+            qout[c * npts + p] = cmk<double2>(gq, 0.0);
+        }
+    }
+    reduce_store<5>(acc, part);
+}
+
+// sums <y, rho Phi>, <y, (S.s) Phi> (y real part) and the V gradient
+__global__ void __launch_bounds__(RB2) k_grad_final(long long npts, const double* __restrict__ phi,
+                                                    const double2* __restrict__ y, const double* __restrict__ dens,
+                                                    double s, double* __restrict__ dV, double* part) {
+    const double r2 = 0.70710678118654752440;
+    double acc[2] = {0, 0};
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x) {
+        const double a = phi[p], b = phi[npts + p], d = phi[2 * npts + p];
+        const double ya = y[p].x, yb = y[npts + p].x, yd = y[2 * npts + p].x;
+        const double rho = a * a + b * b + d * d;
+        const double sx = 1.4142135623730950488 * b * (a + d), sz = a * a - d * d;
+        // (S.s) Phi = sx S_x Phi + sz S_z Phi
+        const double sp0 = sx * r2 * b + sz * a, sp1 = sx * r2 * (a + d), sp2 = sx * r2 * b - sz * d;
+        acc[0] += rho * (ya * a + yb * b + yd * d);
+        acc[1] += ya * sp0 + yb * sp1 + yd * sp2;
+        dV[p] = s * dens[p] - (ya * a + yb * b + yd * d);
+    }
+    reduce_store<2>(acc, part);
+}
+
+__global__ void k_axpy_real_cols(long long n, double a1, const double* __restrict__ x1, double a2,
+                                 const double* __restrict__ x2, double2* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = cmk<double2>(a1 * x1[i] + a2 * x2[i], 0.0);
+}
+
+__global__ void k_szphi(long long npts, const double* __restrict__ phi, double* __restrict__ out) {
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x) {
+        out[p] = phi[p];
+        out[npts + p] = 0.0;
+        out[2 * npts + p] = -phi[2 * npts + p];
+    }
+}
+
+__global__ void k_scale_add(long long n, double s, const double2* __restrict__ x, double2* __restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double2 a = x[i], b = y[i];
+        y[i] = cmk<double2>(b.x + s * a.x, b.y + s * a.y);
+    }
+}
+
+__global__ void k_mean_rows(long long npts, int j0, int cnt, double* __restrict__ dV) {
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x) {
+        double a = 0;
+        for (int j = 0; j < cnt; ++j) a += dV[(long long)(j0 + j) * npts + p];
+        a /= cnt;
+        for (int j = 0; j < cnt; ++j) dV[(long long)(j0 + j) * npts + p] = a;
+    }
+}
+
+}  // namespace
+
+extern "C" bdg_status bdg_eigs_grad(bdg_ctx* c, int k, const double* omega, const void* UV_dev, double* dV_dev,
+                                    double* dbeta_n, double* dbeta_s) {
+    if (!c) return BDG_EINVAL;
+    if (k < 1 || !omega || !UV_dev || !dV_dev || !dbeta_n || !dbeta_s)
+        return ctx_fail(c, BDG_EINVAL, "bdg_eigs_grad: bad arguments");
+    if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "bdg_eigs_grad: no ground state set");
+    const long long npts = c->npts, nh = 3 * npts;
+    const bdg_problem& pr = c->prob;
+    Small w;
+    BDG_TRY(small_alloc(c, w, 8));
+    double2* Q = nullptr;      // orthonormal basis of span{Phi, S_z Phi} (complex, 2 columns)
+    double* szphi = nullptr;
+    double* dens = nullptr;
+    double2* qv = nullptr;     // q, then the right-hand side
+    double2* y = nullptr;
+    double2* yc = nullptr;
+    double2* ws = nullptr;
+    double* part = nullptr;
+    double* sums = nullptr;
+    const int nblk = (int)std::min<long long>(1024, (npts + RB2 - 1) / RB2);
+    BDG_TRY(ctx_alloc(c, (void**)&Q, 2 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&szphi, nh * sizeof(double)));
+    BDG_TRY(ctx_alloc(c, (void**)&dens, npts * sizeof(double)));
+    BDG_TRY(ctx_alloc(c, (void**)&qv, nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&y, nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&yc, 2 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&ws, 5 * nh * sizeof(double2)));
+    BDG_TRY(ctx_alloc(c, (void**)&part, 8 * (size_t)nblk * sizeof(double)));
+    BDG_TRY(ctx_alloc(c, (void**)&sums, 8 * sizeof(double)));
+    auto reduce = [&](int nq, double* host, double scale) -> bdg_status {
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, c->stream, nq, nblk, (const double*)part, scale, sums);
+        return d2h(c, host, sums, nq * sizeof(double));
+    };
+    // tangent-space basis: Phi and S_z Phi (orthonormalized; S_z Phi may vanish)
+    hipLaunchKernelGGL(k_szphi, dim3(nblk), dim3(RB2), 0, c->stream, npts, (const double*)c->phi, szphi);
+    hipLaunchKernelGGL(k_axpy_real_cols, dim3(nblk), dim3(RB2), 0, c->stream, nh, 1.0, (const double*)c->phi, 0.0,
+                       (const double*)c->phi, yc);
+    hipLaunchKernelGGL(k_axpy_real_cols, dim3(nblk), dim3(RB2), 0, c->stream, nh, 1.0, (const double*)szphi, 0.0,
+                       (const double*)szphi, yc + nh);
+    int nq = 0;
+    BDG_TRY(orthonormalize(c, w, nh, yc, 2, Q, 1e-12, &nq));
+    // Gram of the raw constraint vectors (for the component of y along them)
+    double g11, g12, g22;
+    {
+        bdg_status st;
+        g11 = host_dot_re(c, w, nh, yc, yc, &st); BDG_TRY(st);
+        g12 = host_dot_re(c, w, nh, yc, yc + nh, &st); BDG_TRY(st);
+        g22 = host_dot_re(c, w, nh, yc + nh, yc + nh, &st); BDG_TRY(st);
+    }
+    const double shift = 20.0;
+    std::vector<double> gbn(k), gbs(k);
+    for (int j = 0; j < k; ++j) {
+        const double2* uv = (const double2*)UV_dev + (size_t)j * 2 * nh;
+        hipLaunchKernelGGL(k_grad_fields, dim3(nblk), dim3(RB2), 0, c->stream, npts, (const double*)c->phi, uv,
+                           pr.beta_n, pr.beta_s, dens, qv, part);
+        double sm[5];
+        BDG_TRY(reduce(5, sm, c->hd));
+        if (!(sm[0] > 0)) return ctx_fail(c, BDG_EINVAL, "bdg_eigs_grad: <f, g> <= 0 (not a positive excitation)");
+        const double s = 1.0 / (2.0 * sm[0]);
+        const double a_mu = -s * sm[3], a_lam = -s * sm[4];
+        // y_c = c1 Phi + c2 S_z Phi with <Phi, y_c> = -a_mu, <S_z Phi, y_c> = -a_lam
+        double c1 = 0, c2 = 0;
+        const double det = g11 * g22 - g12 * g12;
+        if (det > 1e-14 * g11 * g22) {
+            c1 = (-a_mu * g22 + a_lam * g12) / det;
+            c2 = (-a_lam * g11 + a_mu * g12) / det;
+        } else {
+            c1 = -a_mu / g11;
+        }
+        // rhs = s q - H_+ y_c, solve H_+ t = rhs on the tangent space, y = y_c + t
+        hipLaunchKernelGGL(k_axpy_real_cols, dim3(nblk), dim3(RB2), 0, c->stream, nh, c1, (const double*)c->phi, c2,
+                           (const double*)szphi, y);
+        BDG_TRY(apply64(c, 1, y, y, nh, ws, ws + nh));          // ws = H_+ y_c
+        // qv <- s qv - H_+ y_c
+        {
+            double sv = s;
+            BDG_TRY(h2d(c, sums, &sv, sizeof(double)));
+            hipLaunchKernelGGL(k_cols_scale, grid_cols(nh, 1), dim3(256), 0, c->stream, nh, 1, qv, nh,
+                               (const double*)sums, 0);
+        }
+        hipLaunchKernelGGL(k_scale_add, dim3(nblk), dim3(RB2), 0, c->stream, nh, -1.0, (const double2*)ws, qv);
+        double2* t = yc;   // reuse
+        BDG_TRY(pcg_hplus(c, w, nh, Q, nq, qv, t, ws, shift, 1e-12, 20000));
+        hipLaunchKernelGGL(k_scale_add, dim3(nblk), dim3(RB2), 0, c->stream, nh, 1.0, (const double2*)t, y);
+        double* dVj = dV_dev + (size_t)j * npts;
+        hipLaunchKernelGGL(k_grad_final, dim3(nblk), dim3(RB2), 0, c->stream, npts, (const double*)c->phi,
+                           (const double2*)y, (const double*)dens, s, dVj, part);
+        double fin[2];
+        BDG_TRY(reduce(2, fin, c->hd));
+        gbn[j] = s * sm[1] - fin[0];
+        gbs[j] = s * sm[2] - fin[1];
+        // restore yc columns (reused as PCG output) for the next eigenpair
+        hipLaunchKernelGGL(k_axpy_real_cols, dim3(nblk), dim3(RB2), 0, c->stream, nh, 1.0, (const double*)c->phi, 0.0,
+                           (const double*)c->phi, yc);
+        hipLaunchKernelGGL(k_axpy_real_cols, dim3(nblk), dim3(RB2), 0, c->stream, nh, 1.0, (const double*)szphi, 0.0,
+                           (const double*)szphi, yc + nh);
+    }
+    // cluster means (|omega_i - omega_j| <= 1e-8 omega)
+    int j0 = 0;
+    while (j0 < k) {
+        int j1 = j0 + 1;
+        while (j1 < k && std::fabs(omega[j1] - omega[j0]) <= 1e-8 * std::fabs(omega[j0])) ++j1;
+        const int cnt = j1 - j0;
+        double mbn = 0, mbs = 0;
+        for (int j = j0; j < j1; ++j) { mbn += gbn[j]; mbs += gbs[j]; }
+        for (int j = j0; j < j1; ++j) { dbeta_n[j] = mbn / cnt; dbeta_s[j] = mbs / cnt; }
+        if (cnt > 1)
+            hipLaunchKernelGGL(k_mean_rows, dim3(nblk), dim3(RB2), 0, c->stream, npts, j0, cnt, dV_dev);
+        j0 = j1;
+    }
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    small_free(c, w);
+    for (void* p : {(void*)Q, (void*)szphi, (void*)dens, (void*)qv, (void*)y, (void*)yc, (void*)ws, (void*)part,
+                    (void*)sums})
+        ctx_free(c, p);
+    return BDG_OK;
+}
