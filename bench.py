@@ -88,8 +88,9 @@ def cpu_baseline(w, gpu_iters, budget_s=20.0):
     r = gs.ground_state(V, ws.beta_n, ws.beta_s, ws.mass, ws.magnetization, ws.n, ws.L, W.initial_spinor(ws),
                         tol=1e-10, max_iter=5000)
     coef = bdg.coefficients(r.phi, r.mu, V, ws.beta_n, ws.beta_s)
-    prob = lrep.LrepProblem(coef, ws.n, ws.L)
-    Nm, Qg = lrep.deflation_sets(prob, r.phi, cg_tol=1e-10)
+    sigma, D = lrep.preconditioner_parameters(V, r.mu)
+    prob = lrep.LrepProblem(coef, ws.n, ws.L, D)
+    Nm, Qg = lrep.deflation_sets(prob, r.phi, cg_tol=1e-10, sigma=sigma)
     X0 = W.start_block(ws)
     # time iterations of the subspace iteration (set-up excluded)
     iters = 0
@@ -97,7 +98,7 @@ def cpu_baseline(w, gpu_iters, budget_s=20.0):
     per_it = None
     for n_it in (2, 4, 8):
         t1 = time.time()
-        lrep.lrep_eigs(prob, ws.k, X0, 1e-30, max_iter=n_it, Nm=Nm, Qg=Qg)
+        lrep.lrep_eigs(prob, ws.k, X0, 1e-30, max_iter=n_it, Nm=Nm, Qg=Qg, sigma=sigma)
         dt = time.time() - t1
         per_it = dt / n_it
         iters = n_it

@@ -113,8 +113,11 @@ bdg_status bdg_biortho(bdg_ctx* ctx, int nvec, void* F_dev, void* G_dev, double*
 
 /* k smallest strictly positive excitation frequencies (Section 3.2): block subspace
  * iteration on [[0, H_-], [H_+, 0]] with deflation of the generalized nullspace
- * (Section 2.3), bi-orthogonal Gram-Schmidt, Rayleigh-Ritz projection and the
- * preconditioner (|k|^2/2 + sigma)^-1.  Converged when every wanted column has
+ * (Section 2.3), bi-orthogonal Gram-Schmidt and Rayleigh-Ritz projection.  Corrections
+ * use the kinetic-potential preconditioner D (|k|^2/2 + sigma)^-1 D with
+ * sigma = max(mu_0 / 2, 1/2) and D^2 = sigma / (sigma + max(V - mu_0, 0)) (mu_0: the
+ * middle chemical potential); columns whose residual is already <= tol get no correction
+ * (soft locking).  Converged when every wanted column has
  *   res_j = ||(H_- g_j - w_j f_j, H_+ f_j - w_j g_j)|| / (|w_j| ||(f_j, g_j)||) <= tol,
  * checked with a float64 apply at the end.
  * X0_dev: block x 6 npts complex128 start block in (f, g) form (NULL = complex normal
@@ -133,7 +136,10 @@ bdg_status bdg_eigs(bdg_ctx* ctx, int k, int block, double tol, int max_iter,
  * (the functional derivative), dbeta_n[k] and dbeta_s[k] (host) the derivatives with
  * respect to beta_n and beta_s.  The ground state must have been computed by
  * bdg_ground_state or installed with bdg_set_ground_state.  Eigenvalues within
- * 1e-8 omega of each other form a cluster and receive the cluster-mean gradient. */
+ * 1e-8 omega of each other form a cluster and receive the cluster-mean gradient (the
+ * derivative of the cluster's mean frequency).  A cluster that continues past index k
+ * is cut: its members' gradients then depend on the basis inside the eigenspace, so
+ * choose k at a gap of the spectrum. */
 bdg_status bdg_eigs_grad(bdg_ctx* ctx, int k, const double* omega, const void* UV_dev,
                          double* dV_dev, double* dbeta_n, double* dbeta_s);
 

@@ -15,8 +15,14 @@ following steps, each in plain numpy:
               where H_+ Phi_hat = n for n in N_- (Jordan partners): the eigenvectors with
               omega != 0 are J-orthogonal to the generalized nullspace;
   residual    R_f = H_- G - F Theta, R_g = H_+ F - G Theta;
-  correction  W_f = T R_g, W_g = T R_f with T = (|k|^2/2 + sigma)^-1 (the gradient of
-              the minimization-principle quotient with respect to f is H_+ f - omega g);
+  correction  W_f = T R_g, W_g = T R_f (the gradient of the minimization-principle
+              quotient with respect to f is H_+ f - omega g).  The paper prints no
+              preconditioner; T is the symmetric kinetic-potential product
+              T = D (|k|^2/2 + sigma)^-1 D,  D(x)^2 = sigma / (sigma + max(V(x) - mu, 0)),
+              sigma = max(mu / 2, 1/2), the combination used by the preconditioned
+              ground-state solvers the paper cites (Section 1): the Fourier factor
+              handles the kinetic part, D the trap far outside the condensate where
+              V - mu dominates.  Without V (a bare coefficient set) D = 1, sigma = 20;
   bi-orth     B_r = S_g^H S_f = U Sigma V^H, C_f = V Sigma^-1/2, C_g = U Sigma^-1/2
               (rank drop when sigma_i < 1e-8 sigma_1), so (S_g C_g)^H (S_f C_f) = I;
   Rayleigh-Ritz  M~ = C_f^H S_f^H H_+ S_f C_f = L_M L_M^H, K~ = C_g^H S_g^H H_- S_g C_g
@@ -93,11 +99,22 @@ def _k_apply(op_symbol, X3, grid_shape):
     return out.reshape(ncol, -1).T
 
 
-class LrepProblem:
-    """Operator access on column blocks: columns of F / G are flattened 3-component fields."""
+def preconditioner_parameters(V, mu):
+    """(sigma, D) of the kinetic-potential preconditioner: sigma = max(mu_0 / 2, 1/2) with
+    mu_0 the middle chemical potential, D = sqrt(sigma / (sigma + max(V - mu_0, 0)))."""
+    mu0 = float(np.asarray(mu, dtype=np.float64)[1])
+    sigma = max(0.5 * mu0, 0.5)
+    U = np.maximum(np.asarray(V, dtype=np.float64) - mu0, 0.0)
+    return sigma, np.sqrt(sigma / (sigma + U))
 
-    def __init__(self, coef: bdg.Coefficients, n, L):
+
+class LrepProblem:
+    """Operator access on column blocks: columns of F / G are flattened 3-component fields.
+    weight: optional pointwise factor D of the preconditioner (grid shape)."""
+
+    def __init__(self, coef: bdg.Coefficients, n, L, weight=None):
         self.coef, self.n, self.L = coef, tuple(n), tuple(L)
+        self.weight = None if weight is None else np.tile(np.asarray(weight, dtype=np.float64).ravel(), 3)[:, None]
         self.grid_shape = tuple(reversed(n))
         self.h = tuple(2.0 * Li / ni for ni, Li in zip(n, L))
         self.hd = float(np.prod(self.h))
@@ -123,7 +140,10 @@ class LrepProblem:
         return self._fields_to_cols(bdg.apply_hminus(self.coef, self._cols_to_fields(G), self.n, self.L, self.Hm))
 
     def precond(self, R, sigma):
-        return _k_apply(1.0 / (self.sym + sigma), R, self.grid_shape)
+        """D (|k|^2/2 + sigma)^-1 D on every column (D = 1 without a weight)."""
+        if self.weight is None:
+            return _k_apply(1.0 / (self.sym + sigma), R, self.grid_shape)
+        return self.weight * _k_apply(1.0 / (self.sym + sigma), self.weight * R, self.grid_shape)
 
 
 def null_candidates(phi):
@@ -283,9 +303,17 @@ def lrep_eigs(prob: LrepProblem, k: int, X0: np.ndarray, tol: float, max_iter: i
     return LrepResult(omega=om[:k], X=X[:k], residual=res[:k], iters=it, history=history)
 
 
-def solve(coef, phi, n, L, k, X0, tol, max_iter=1000, sigma=20.0, verbose=False):
-    """Deflation sets + subspace iteration in one call."""
-    prob = LrepProblem(coef, n, L)
+def solve(coef, phi, n, L, k, X0, tol, max_iter=1000, sigma=None, verbose=False, V=None, mu=None):
+    """Deflation sets + subspace iteration in one call.  With V and mu the
+    kinetic-potential preconditioner is used (sigma from preconditioner_parameters unless
+    given), otherwise the kinetic one with sigma = 20."""
+    weight = None
+    if V is not None and mu is not None:
+        s0, weight = preconditioner_parameters(V, mu)
+        sigma = s0 if sigma is None else sigma
+    elif sigma is None:
+        sigma = 20.0
+    prob = LrepProblem(coef, n, L, weight)
     Nm, Qg = deflation_sets(prob, phi, sigma=sigma)
     out = lrep_eigs(prob, k, X0, tol, max_iter=max_iter, Nm=Nm, Qg=Qg, sigma=sigma,
                     verbose=verbose)

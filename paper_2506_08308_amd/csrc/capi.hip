@@ -3,6 +3,7 @@
 // bdg_set_ground_state, bdg_apply, bdg_stats).
 #include "common.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -80,9 +81,11 @@ __global__ void k_check_finite(long long n, const double* __restrict__ v, int* f
 //   H_+ = V - Lambda + beta_n (rho I + 2 Phi Phi^T)
 //         + beta_s (S.s + 2 (S_x Phi)(S_x Phi)^T + 2 (S_z Phi)(S_z Phi)^T),
 //   H_- = V - Lambda + beta_n rho I + beta_s (S.s + 2 (K Phi)(K Phi)^T).
+// Also the pointwise factor of the eigensolver's preconditioner,
+//   D = sqrt(ps / (ps + max(V - mu_0, 0))).
 __global__ void k_coef(long long npts, const double* __restrict__ V, const double* __restrict__ phi, double mu1,
                        double mu0, double mum, double bn, double bs, double* __restrict__ c64,
-                       float* __restrict__ c32) {
+                       float* __restrict__ c32, double ps, double* __restrict__ w64, float* __restrict__ w32) {
     const double r2 = 0.70710678118654752440;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
          p += (long long)gridDim.x * blockDim.x) {
@@ -114,6 +117,10 @@ __global__ void k_coef(long long npts, const double* __restrict__ V, const doubl
             c32[s * npts + p] = (float)P[s];
             c32[(6 + s) * npts + p] = (float)M[s];
         }
+        const double u = vp - mu0 > 0.0 ? vp - mu0 : 0.0;
+        const double dw = sqrt(ps / (ps + u));
+        w64[p] = dw;
+        w32[p] = (float)dw;
     }
 }
 
@@ -123,8 +130,9 @@ bdg_status build_coefficients(bdg_ctx* c) {
     const bdg_problem& pr = c->prob;
     const long long n = c->npts;
     int blocks = (int)std::min<long long>(4096, (n + 255) / 256);
+    c->pshift = std::max(0.5 * c->mu[1], 0.5);
     hipLaunchKernelGGL(k_coef, dim3(blocks), dim3(256), 0, c->stream, n, c->V, c->phi, c->mu[0], c->mu[1],
-                       c->mu[2], pr.beta_n, pr.beta_s, c->coef64, c->coef32);
+                       c->mu[2], pr.beta_n, pr.beta_s, c->coef64, c->coef32, c->pshift, c->pw64, c->pw32);
     return hip_check(c, hipGetLastError(), "k_coef");
 }
 
@@ -177,6 +185,8 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     if (ctx_alloc(c, (void**)&c->phi, 3 * n * sizeof(double)) != BDG_OK) return fail(BDG_ENOMEM);
     if (ctx_alloc(c, (void**)&c->coef64, 12 * n * sizeof(double)) != BDG_OK) return fail(BDG_ENOMEM);
     if (ctx_alloc(c, (void**)&c->coef32, 12 * n * sizeof(float)) != BDG_OK) return fail(BDG_ENOMEM);
+    if (ctx_alloc(c, (void**)&c->pw64, n * sizeof(double)) != BDG_OK) return fail(BDG_ENOMEM);
+    if (ctx_alloc(c, (void**)&c->pw32, n * sizeof(float)) != BDG_OK) return fail(BDG_ENOMEM);
     if (hipMemcpyAsync(c->V, V_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
         return fail(BDG_EDEVICE);
     // finiteness of V

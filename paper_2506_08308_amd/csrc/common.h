@@ -55,6 +55,11 @@ struct bdg_ctx {
     bool has_gs = false;
     double* coef64 = nullptr;     // 12 npts: H_+ (6 sym entries) then H_- (6), V - mu folded in
     float* coef32 = nullptr;      // same, rounded
+    // kinetic-potential preconditioner D (|k|^2/2 + pshift)^-1 D of the eigensolver:
+    // pshift = max(mu_0 / 2, 1/2), D = sqrt(pshift / (pshift + max(V - mu_0, 0)))
+    double pshift = 20.0;
+    double* pw64 = nullptr;       // D, npts
+    float* pw32 = nullptr;
     double2* tw64[3] = {nullptr, nullptr, nullptr};   // exp(-2 pi i m / N_a), m < N_a
     float2* tw32[3] = {nullptr, nullptr, nullptr};
     double* sym64[3] = {nullptr, nullptr, nullptr};   // mu_m^2 / 2 per axis, FFT order
@@ -101,16 +106,19 @@ template <typename R>
 bdg_status launch_apply(bdg_ctx* c, int form, int transpose, int nvec,
                         BlockRef<const typename cplx_of<R>::type> X, BlockRef<typename cplx_of<R>::type> Y);
 
-// Y = T X with T = (|k|^2/2 + shift)^-1 on `nfields` complex grid fields;
+// Y = T X with the eigensolver's preconditioner T = D (|k|^2/2 + pshift)^-1 D (context
+// fields, set with the ground state) on `nfields` complex grid fields;
 // field f at base + (f / fpv) * vstride + (f % fpv) * npts.  X and Y may alias.
 template <typename R>
 bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
-                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, double shift);
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y);
 
-// Y = F^-1 m(k) F X with m = |k|^2/2 (precond = 0) or (|k|^2/2 + shift)^-1 (precond = 1).
+// Y = D F^-1 m(k) F D X with m = |k|^2/2 (precond = 0) or (|k|^2/2 + shift)^-1
+// (precond = 1); D = wgt (npts real, pointwise) or 1 when wgt is null.
 template <typename R>
 bdg_status launch_fourier(bdg_ctx* c, int nfields, int fpv, long long vstride,
-                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, int precond, double shift);
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, int precond, double shift,
+                          const R* wgt);
 
 // Plain forward/inverse (unnormalized) d-dimensional FFT of nfields fields (tests, ground state).
 template <typename R>
@@ -141,6 +149,9 @@ bdg_status gram(bdg_ctx* c, long long K, int m1, int m2, const TA* A, long long 
 // column stride lds each; Cm device m x nb column-major (ldcm); Y column stride ldy.
 bdg_status update(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds,
                   const double2* Cm, int ldcm, int nb, double beta, double2* Y, long long ldy);
+// Y = S Cm + beta Z (Z may equal Y; Y must not overlap S when nb > 80).
+bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cm,
+                      int ldcm, int nb, double beta, const double2* Z, long long ldz, double2* Y, long long ldy);
 
 // small dense FP64 complex matrices on the device (column-major)
 bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, double2 alpha,
@@ -163,3 +174,7 @@ bdg_status small_plu_biorth(bdg_ctx* c, int p, int q, double2* B, int ldb, doubl
 // column norms squared (deterministic), etc.
 bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx,
                     double* out_dev);
+// residual norms of ncols columns (stride ld) in one pass: out_dev[q * ncols + j] holds
+// |HF_j - om_j G_j|^2 (q = 0), |HG_j - om_j F_j|^2 (1), |F_j|^2 (2), |G_j|^2 (3)
+bdg_status resnorm2(bdg_ctx* c, long long K, int ncols, const double2* HF, const double2* G, const double2* HG,
+                    const double2* F, long long ld, const double* om_dev, double* out_dev);

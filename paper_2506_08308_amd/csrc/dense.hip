@@ -151,13 +151,15 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
 }
 
 // ----------------------------------------------------------------------------------------
-// Update: Y (K x nb) = S (K x m) Cm (m x nb) + beta Y.  Each wave: 32 rows x 16*CB columns.
+// Update: Y (K x nb) = S (K x m) Cm (m x nb) + beta Z.  Each wave: 32 rows x 16*CB columns.
 //   Re Y = Re S Re C - Im S Im C,  Im Y = Re S Im C + Im S Re C.
+// Z may be Y (each element is read before it is written by the same lane); Y must not
+// overlap S unless one workgroup covers all nb columns (grid.y == 1).
 // ----------------------------------------------------------------------------------------
 template <int CB>
 __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long long lds, int m,
                                                 const double2* __restrict__ Cm, int ldcm, int nb, double beta,
-                                                double2* __restrict__ Y, long long ldy) {
+                                                const double2* Z, long long ldz, double2* Y, long long ldy) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const long long r0 = ((long long)blockIdx.x * 4 + wave) * 32;
     const int j0 = blockIdx.y * 16 * CB;
@@ -207,16 +209,15 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
             for (int r = 0; r < 4; ++r) {
                 const long long row = r0 + 16 * a + 4 * r + (lane >> 4);
                 if (row >= K) continue;
-                double2* dst = Y + (long long)j * ldy + row;
                 double2 v;
                 v.x = accr[a][b][r];
                 v.y = acci[a][b][r];
                 if (beta != 0.0) {
-                    double2 o = *dst;
+                    const double2 o = Z[(long long)j * ldz + row];
                     v.x += beta * o.x;
                     v.y += beta * o.y;
                 }
-                *dst = v;
+                Y[(long long)j * ldy + row] = v;
             }
         }
 }
@@ -505,6 +506,45 @@ __global__ void __launch_bounds__(RB) k_colnorm2_part(long long K, const double2
     }
 }
 
+// Residual norms of a block in one pass: for column j (omega_j = om[j]) the partial sums of
+// |HF - w G|^2, |HG - w F|^2, |F|^2, |G|^2 into part[((q * ncols) + j) * nchunk + chunk].
+__global__ void __launch_bounds__(RB) k_resnorm2_part(long long K, const double2* __restrict__ HF,
+                                                      const double2* __restrict__ G, const double2* __restrict__ HG,
+                                                      const double2* __restrict__ F, long long ld,
+                                                      const double* __restrict__ om, long long kper,
+                                                      double* __restrict__ part) {
+    __shared__ double red[4][RB / 64];
+    const int col = blockIdx.y, chunk = blockIdx.x, ncols = gridDim.y;
+    const long long k0 = chunk * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const long long off = (long long)col * ld;
+    const double w = om[col];
+    double s[4] = {0, 0, 0, 0};
+    for (long long k = k0 + threadIdx.x; k < k1; k += RB) {
+        const double2 hf = HF[off + k], g = G[off + k], hg = HG[off + k], f = F[off + k];
+        const double a = hf.x - w * g.x, b = hf.y - w * g.y;
+        const double cc = hg.x - w * f.x, d = hg.y - w * f.y;
+        s[0] += a * a + b * b;
+        s[1] += cc * cc + d * d;
+        s[2] += f.x * f.x + f.y * f.y;
+        s[3] += g.x * g.x + g.y * g.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double v = s[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        double a = 0;
+        for (int wv = 0; wv < RB / 64; ++wv) a += red[q][wv];
+        part[((long long)q * ncols + col) * gridDim.x + chunk] = a;
+    }
+}
+
 __global__ void k_colnorm2_final(int ncols, int nchunk, const double* __restrict__ part, double* out) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= ncols) return;
@@ -569,6 +609,11 @@ bdg_status gram<double2, double2>(bdg_ctx* c, long long K, int m1, int m2, const
 
 bdg_status update(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cm, int ldcm,
                   int nb, double beta, double2* Y, long long ldy) {
+    return update_add(c, K, segs, nseg, lds, Cm, ldcm, nb, beta, Y, ldy, Y, ldy);
+}
+
+bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cm,
+                      int ldcm, int nb, double beta, const double2* Z, long long ldz, double2* Y, long long ldy) {
     if (nb <= 0 || K <= 0) return BDG_OK;
     SegList sl;
     int m = 0;
@@ -577,11 +622,11 @@ bdg_status update(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long 
     const int ctiles = (nb + 16 * cb - 1) / (16 * cb);
     dim3 grid((unsigned)((K + 127) / 128), (unsigned)ctiles);
     switch (cb) {
-        case 1: hipLaunchKernelGGL(k_update<1>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
-        case 2: hipLaunchKernelGGL(k_update<2>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
-        case 3: hipLaunchKernelGGL(k_update<3>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
-        case 4: hipLaunchKernelGGL(k_update<4>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
-        default: hipLaunchKernelGGL(k_update<5>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Y, ldy); break;
+        case 1: hipLaunchKernelGGL(k_update<1>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
+        case 2: hipLaunchKernelGGL(k_update<2>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
+        case 3: hipLaunchKernelGGL(k_update<3>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
+        case 4: hipLaunchKernelGGL(k_update<4>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
+        default: hipLaunchKernelGGL(k_update<5>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
     }
     return hip_check(c, hipGetLastError(), "k_update");
 }
@@ -659,4 +704,20 @@ bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long l
     hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((ncols + 127) / 128)), dim3(128), 0, c->stream, ncols,
                        nchunk, (const double*)ws, out_dev);
     return hip_check(c, hipGetLastError(), "k_colnorm2");
+}
+
+bdg_status resnorm2(bdg_ctx* c, long long K, int ncols, const double2* HF, const double2* G, const double2* HG,
+                    const double2* F, long long ld, const double* om_dev, double* out_dev) {
+    if (ncols <= 0) return BDG_OK;
+    int nchunk = (int)std::min<long long>(128, (K + 8191) / 8192);
+    if (nchunk < 1) nchunk = 1;
+    const long long kper = (K + nchunk - 1) / nchunk;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 2, (size_t)4 * ncols * nchunk * sizeof(double), &ws));
+    hipLaunchKernelGGL(k_resnorm2_part, dim3((unsigned)nchunk, (unsigned)ncols), dim3(RB), 0, c->stream, K, HF, G, HG,
+                       F, ld, om_dev, kper, (double*)ws);
+    BDG_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((4 * ncols + 127) / 128)), dim3(128), 0, c->stream,
+                       4 * ncols, nchunk, (const double*)ws, out_dev);
+    return hip_check(c, hipGetLastError(), "k_resnorm2");
 }

@@ -108,10 +108,13 @@ __device__ __forceinline__ R multiplier(const MultSpec& m, int mx, int my, int m
 // x pass: contiguous lines.  MODE 0: plain FFT (direction INV); MODE 1: fused forward,
 // multiplier, inverse (the x axis is the only axis: 1-D preconditioner / plain fused use).
 // ----------------------------------------------------------------------------------------
+// wgt (optional, npts real): pointwise factor applied before a forward transform and after
+// an inverse one (the D of a symmetric preconditioner D T D).
 template <typename V, int N, bool INV, int MODE>
 __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<V> out,
                                                long long nfields, long long lines_per_field,
-                                               const V* __restrict__ tw, MultSpec ms, int ny) {
+                                               const V* __restrict__ tw, MultSpec ms, int ny,
+                                               const decltype(V::x)* __restrict__ wgt) {
     using R = decltype(V::x);
     constexpr int Q = N / 4;
     constexpr int LPW = (1024 / N) > 0 ? (1024 / N) : 1;
@@ -127,6 +130,17 @@ __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<
     V v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+    R wv[4] = {1, 1, 1, 1};
+    if (wgt != nullptr && valid) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wv[r] = wgt[l * N + i + r * Q];
+    }
+    const bool wfwd = wgt != nullptr && (MODE == 1 || !INV);
+    const bool winv = wgt != nullptr && (MODE == 1 || INV);
+    if (wfwd) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], wv[r]);
+    }
     if (MODE == 0) {
         line_fft<V, N, INV>(v, i, lds, ln * N, 1, tw);
     } else {
@@ -135,6 +149,10 @@ __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], multiplier<R>(ms, i + r * Q, my, mz));
         line_fft<V, N, true>(v, i, lds, ln * N, 1, tw);
+    }
+    if (winv) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], wv[r]);
     }
     if (valid) {
 #pragma unroll
@@ -350,7 +368,8 @@ MultSpec make_ms(bdg_ctx* c, int precond, double shift) {
     }
 
 template <typename V, bool INV, int MODE>
-bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<V> out, long long nfields, MultSpec ms) {
+bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<V> out, long long nfields, MultSpec ms,
+                     const decltype(V::x)* wgt = nullptr) {
     const int N = c->n[0];
     const long long lpf = c->npts / N;
     BDG_DISPATCH_N(N, {
@@ -358,7 +377,7 @@ bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<V> out, long l
         const long long nl = nfields * lpf;
         dim3 grid((unsigned)((nl + LPW - 1) / LPW));
         hipLaunchKernelGGL((k_xpass<V, NN, INV, MODE>), grid, dim3(LPW * (NN / 4)), 0, c->stream,
-                           in, out, nfields, lpf, (const V*)tw_of<decltype(V::x)>(c, 0), ms, c->n[1]);
+                           in, out, nfields, lpf, (const V*)tw_of<decltype(V::x)>(c, 0), ms, c->n[1], wgt);
     });
     return hip_check(c, hipGetLastError(), "k_xpass");
 }
@@ -427,14 +446,15 @@ bdg_status launch_apply(bdg_ctx* c, int form, int transpose, int nvec,
 
 template <typename R>
 bdg_status launch_fourier(bdg_ctx* c, int nfields, int fpv, long long vstride,
-                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, int precond, double shift) {
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, int precond, double shift,
+                          const R* wgt) {
     using V = typename cplx_of<R>::type;
     if (nfields <= 0) return BDG_OK;
     MultSpec ms = make_ms(c, precond, shift);
     FieldAddr<const V> xa = fa_fields<const V>(X, fpv, vstride, c->npts);
     FieldAddr<V> ya = fa_fields<V>(Y, fpv, vstride, c->npts);
-    if (c->dim == 1) return run_xpass<V, false, 1>(c, xa, ya, nfields, ms);
-    BDG_TRY((run_xpass<V, false, 0>(c, xa, ya, nfields, ms)));
+    if (c->dim == 1) return run_xpass<V, false, 1>(c, xa, ya, nfields, ms, wgt);
+    BDG_TRY((run_xpass<V, false, 0>(c, xa, ya, nfields, ms, wgt)));
     if (c->dim == 2) {
         BDG_TRY((run_strided<V, false, 1>(c, ya, nfields, 1, ms)));
     } else {
@@ -443,7 +463,7 @@ bdg_status launch_fourier(bdg_ctx* c, int nfields, int fpv, long long vstride,
         BDG_TRY((run_strided<V, true, 0>(c, ya, nfields, 1, ms)));
     }
     FieldAddr<const V> yc = fa_fields<const V>(Y, fpv, vstride, c->npts);
-    return run_xpass<V, true, 0>(c, yc, ya, nfields, ms);
+    return run_xpass<V, true, 0>(c, yc, ya, nfields, ms, wgt);
 }
 
 template <typename R>
@@ -467,15 +487,22 @@ bdg_status launch_fft(bdg_ctx* c, int nfields, const typename cplx_of<R>::type* 
 
 template bdg_status launch_apply<double>(bdg_ctx*, int, int, int, BlockRef<const double2>, BlockRef<double2>);
 template bdg_status launch_apply<float>(bdg_ctx*, int, int, int, BlockRef<const float2>, BlockRef<float2>);
+template <typename R> const R* pw_of(bdg_ctx* c);
+template <> const double* pw_of<double>(bdg_ctx* c) { return c->pw64; }
+template <> const float* pw_of<float>(bdg_ctx* c) { return c->pw32; }
+
 template <typename R>
 bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
-                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y, double shift) {
-    return launch_fourier<R>(c, nfields, fpv, vstride, X, Y, 1, shift);
+                          const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y) {
+    if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "preconditioner needs the ground state");
+    return launch_fourier<R>(c, nfields, fpv, vstride, X, Y, 1, c->pshift, pw_of<R>(c));
 }
 
-template bdg_status launch_fourier<double>(bdg_ctx*, int, int, long long, const double2*, double2*, int, double);
-template bdg_status launch_fourier<float>(bdg_ctx*, int, int, long long, const float2*, float2*, int, double);
-template bdg_status launch_precond<double>(bdg_ctx*, int, int, long long, const double2*, double2*, double);
-template bdg_status launch_precond<float>(bdg_ctx*, int, int, long long, const float2*, float2*, double);
+template bdg_status launch_fourier<double>(bdg_ctx*, int, int, long long, const double2*, double2*, int, double,
+                                           const double*);
+template bdg_status launch_fourier<float>(bdg_ctx*, int, int, long long, const float2*, float2*, int, double,
+                                          const float*);
+template bdg_status launch_precond<double>(bdg_ctx*, int, int, long long, const double2*, double2*);
+template bdg_status launch_precond<float>(bdg_ctx*, int, int, long long, const float2*, float2*);
 template bdg_status launch_fft<double>(bdg_ctx*, int, const double2*, double2*, int);
 template bdg_status launch_fft<float>(bdg_ctx*, int, const float2*, float2*, int);

@@ -238,7 +238,7 @@ extern "C" bdg_status bdg_ground_state(bdg_ctx* c, const double* phi0_dev, doubl
     bdg_status st = BDG_ENOCONV;
     for (it = 1; it <= max_iter; ++it) {
         hipLaunchKernelGGL(k_real_to_cplx, dim3(nblk), dim3(GB), 0, c->stream, 3 * npts, (const double*)phi, z);
-        bdg_status s = launch_fourier<double>(c, 3, 3, 3 * npts, z, tz, 0, 0.0);
+        bdg_status s = launch_fourier<double>(c, 3, 3, 3 * npts, z, tz, 0, 0.0, nullptr);
         if (s != BDG_OK) return finish(s);
         hipLaunchKernelGGL(k_gs_rhs, dim3(nblk), dim3(GB), 0, c->stream, npts, (const double*)phi,
                            (const double*)c->V, (const double2*)tz, pr.beta_n, pr.beta_s, hphi);
@@ -262,7 +262,7 @@ extern "C" bdg_status bdg_ground_state(bdg_ctx* c, const double* phi0_dev, doubl
         res = std::sqrt(std::max(r2, 0.0) / mass);
         if (!(res == res)) return finish(ctx_fail(c, BDG_EBREAKDOWN, "ground state: non-finite residual"));
         if (res <= tol) { st = BDG_OK; break; }
-        if ((s = launch_fourier<double>(c, 3, 3, 3 * npts, z, tz, 1, alpha)) != BDG_OK) return finish(s);
+        if ((s = launch_fourier<double>(c, 3, 3, 3 * npts, z, tz, 1, alpha, nullptr)) != BDG_OK) return finish(s);
         hipLaunchKernelGGL(k_gs_step, dim3(nblk), dim3(GB), 0, c->stream, npts, phi, (const double2*)tz, tau, part);
         double a[3];
         if ((s = reduce(3, a)) != BDG_OK) return finish(s);

@@ -40,15 +40,33 @@ bool debug_on() {
     return v == 1;
 }
 
-__global__ void k_cols_axmy(long long K, int ncols, const double2* __restrict__ X, long long ldx,
-                            const double2* __restrict__ Y, long long ldy, const double* __restrict__ w,
-                            double2* __restrict__ Z, long long ldz) {
-    const int j = blockIdx.y;
+// runs a callable when the scope ends (workspace release on every return path)
+template <typename Fn> struct Defer {
+    Fn fn;
+    ~Defer() { fn(); }
+};
+template <typename Fn> Defer<Fn> defer(Fn fn) { return Defer<Fn>{fn}; }
+
+// Z(:, t) = X(:, idx[t]) - w[idx[t]] Y(:, idx[t]) for t < gridDim.y (active columns)
+__global__ void k_cols_axmy_idx(long long K, const double2* __restrict__ X, const double2* __restrict__ Y, long long ld,
+                                const double* __restrict__ w, const int* __restrict__ idx, double2* __restrict__ Z,
+                                long long ldz) {
+    const int t = blockIdx.y;
+    const long long j = idx[t];
     const double s = w[j];
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
-        double2 a = X[j * ldx + i], b = Y[j * ldy + i];
-        Z[j * ldz + i] = cmk<double2>(a.x - s * b.x, a.y - s * b.y);
+        double2 a = X[j * ld + i], b = Y[j * ld + i];
+        Z[t * ldz + i] = cmk<double2>(a.x - s * b.x, a.y - s * b.y);
     }
+}
+
+// Y(:, t) = X(:, idx[t]) for t < gridDim.y; X and Y must not overlap
+__global__ void k_cols_gather(long long K, const double2* __restrict__ X, long long ldx, const int* __restrict__ idx,
+                              double2* __restrict__ Y, long long ldy) {
+    const int t = blockIdx.y;
+    const long long j = idx[t];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x)
+        Y[t * ldy + i] = X[j * ldx + i];
 }
 
 __global__ void k_cols_scale(long long K, int ncols, double2* __restrict__ X, long long ldx, const double* __restrict__ s,
@@ -406,7 +424,7 @@ double host_dot_re(bdg_ctx* c, Small& w, long long nh, const double2* a, const d
 
 // Projected preconditioned CG for H_+ x = b on span(Np)^perp (Jordan partners).
 bdg_status pcg_hplus(bdg_ctx* c, Small& w, long long nh, const double2* Np, int np, const double2* b, double2* x,
-                     double2* ws, double shift, double tol, int max_iter) {
+                     double2* ws, double tol, int max_iter) {
     double2* r = ws;
     double2* z = ws + nh;
     double2* p = ws + 2 * nh;
@@ -416,7 +434,7 @@ bdg_status pcg_hplus(bdg_ctx* c, Small& w, long long nh, const double2* Np, int 
     BDG_HIP(c, hipMemsetAsync(x, 0, nh * sizeof(double2), c->stream));
     BDG_HIP(c, hipMemcpyAsync(r, b, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
     BDG_TRY(project_out(c, w, nh, Np, np, r, 1));
-    BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z, shift));
+    BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z));
     BDG_TRY(project_out(c, w, nh, Np, np, z, 1));
     BDG_HIP(c, hipMemcpyAsync(p, z, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
     bdg_status st;
@@ -437,7 +455,7 @@ bdg_status pcg_hplus(bdg_ctx* c, Small& w, long long nh, const double2* Np, int 
         const double rn = std::sqrt(std::max(0.0, host_dot_re(c, w, nh, r, r, &st)));
         BDG_TRY(st);
         if (rn <= tol * bnorm) return BDG_OK;
-        BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z, shift));
+        BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z));
         BDG_TRY(project_out(c, w, nh, Np, np, z, 1));
         const double rz_new = host_dot_re(c, w, nh, z, r, &st);
         BDG_TRY(st);
@@ -454,7 +472,7 @@ struct Deflation {
     int pg = 0;
 };
 
-bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double shift, double null_tol) {
+bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double null_tol) {
     const long long npts = c->npts, nh = 3 * npts;
     double2* cand = nullptr;
     double2* img = nullptr;
@@ -503,7 +521,7 @@ bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double shift, dou
     double2* qcols = cand;         // [N_+, partners], up to 4 columns
     if (pp) BDG_HIP(c, hipMemcpyAsync(qcols, Np, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
     for (int j = 0; j < ps; ++j)
-        BDG_TRY(pcg_hplus(c, w, nh, Np, pp, src + j * nh, qcols + (pp + j) * nh, ws, shift, 1e-13, 5000));
+        BDG_TRY(pcg_hplus(c, w, nh, Np, pp, src + j * nh, qcols + (pp + j) * nh, ws, 1e-13, 5000));
     BDG_TRY(orthonormalize(c, w, nh, qcols, pp + ps, d.Qg, 1e-10, &d.pg));
     if (debug_on()) {
         fprintf(stderr, "[bdg deflation] |c|^2=(%.3e %.3e %.3e %.3e) |H_- c|^2=(%.3e %.3e %.3e %.3e) |H_+ c|^2=(%.3e %.3e %.3e %.3e)\n",
@@ -574,7 +592,6 @@ extern "C" bdg_status bdg_biortho(bdg_ctx* c, int nvec, void* F_dev, void* G_dev
 namespace {
 
 struct EigsOpts {
-    double shift = 20.0;        // preconditioner shift sigma
     double rtol = 1e-12;        // pivoted-Cholesky cut-off (Schur complement of the scaled Gram)
     double eps = 1e-10;         // LU pivot cut-off of the pairing matrix
     double null_tol = 1e-6;     // nullspace candidate test
@@ -596,28 +613,43 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     for (double& s : c->stats) s = 0;
     // ------------------------------------------------------------------ allocation
     Small w;
-    BDG_TRY(small_alloc(c, w, std::max(m, 8)));
     Basis S;
+    float2* w32 = nullptr;
+    float2* y32 = nullptr;
+    double2* acoef = nullptr;
+    double2* bcoef = nullptr;
+    double* dvec = nullptr;
+    int* d_act = nullptr;
+    Deflation D;
+    // every exit path releases the workspace
+    auto release = defer([&] {
+        small_free(c, w);
+        for (int a = 0; a < 4; ++a) ctx_free(c, S.arr[a]);
+        ctx_free(c, w32);
+        ctx_free(c, y32);
+        ctx_free(c, acoef);
+        ctx_free(c, bcoef);
+        ctx_free(c, dvec);
+        ctx_free(c, d_act);
+        ctx_free(c, D.Nm);
+        ctx_free(c, D.Qg);
+    });
+    BDG_TRY(small_alloc(c, w, std::max(m, 8)));
     S.nh = nh;
     S.nb = nb;
     for (int a = 0; a < 4; ++a) BDG_TRY(ctx_alloc(c, (void**)&S.arr[a], 4 * (size_t)nb * nh * sizeof(double2)));
-    float2* w32 = nullptr;
-    float2* y32 = nullptr;
     if (mixed) {
         BDG_TRY(ctx_alloc(c, (void**)&w32, 2 * (size_t)nb * nh * sizeof(float2)));
         BDG_TRY(ctx_alloc(c, (void**)&y32, 2 * (size_t)nb * nh * sizeof(float2)));
     }
-    double2* acoef = nullptr;
-    double2* bcoef = nullptr;
-    double* dvec = nullptr;
     BDG_TRY(ctx_alloc(c, (void**)&acoef, (size_t)m * nb * sizeof(double2)));
     BDG_TRY(ctx_alloc(c, (void**)&bcoef, (size_t)m * nb * sizeof(double2)));
     BDG_TRY(ctx_alloc(c, (void**)&dvec, 8 * (size_t)nb * sizeof(double)));
+    BDG_TRY(ctx_alloc(c, (void**)&d_act, (size_t)nb * sizeof(int)));
     double* d_om = dvec;
     double* d_n = dvec + nb;      // 4 nb norms
     // ------------------------------------------------------------------ deflation
-    Deflation D;
-    BDG_TRY(build_deflation(c, w, D, opt.shift, opt.null_tol));
+    BDG_TRY(build_deflation(c, w, D, opt.null_tol));
     auto t_setup = std::chrono::steady_clock::now();
     c->stats[6] = std::chrono::duration<double, std::milli>(t_setup - t_start).count();
     // ------------------------------------------------------------------ start block
@@ -700,6 +732,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         if (timing) BDG_HIP(c, hipStreamSynchronize(c->stream));
         return BDG_OK;
     };
+    std::vector<int> act;
     for (it = 1; it <= max_iter; ++it) {
         F = S.col(SF, S.slotF);
         G = S.col(SG, S.slotF);
@@ -708,26 +741,22 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         double2* Wf = S.col(SF, S.slotW);
         double2* Wg = S.col(SG, S.slotW);
         auto t0 = now();
-        // residual directions and norms
+        // residual norms of every column in one pass over F, G and their images
         BDG_TRY(h2d(c, d_om, om.data(), nb * sizeof(double)));
-        hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)HF, nh,
-                           (const double2*)G, nh, (const double*)d_om, Wf, nh);
-        hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)HG, nh,
-                           (const double2*)F, nh, (const double*)d_om, Wg, nh);
-        BDG_TRY(colnorm2(c, nh, nb, Wf, nh, d_n));
-        BDG_TRY(colnorm2(c, nh, nb, Wg, nh, d_n + nb));
-        BDG_TRY(colnorm2(c, nh, nb, F, nh, d_n + 2 * nb));
-        BDG_TRY(colnorm2(c, nh, nb, G, nh, d_n + 3 * nb));
+        BDG_TRY(resnorm2(c, nh, nb, HF, G, HG, F, nh, d_om, d_n));
         BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
         double rmax = 0;
+        act.clear();
         for (int j = 0; j < nb; ++j) {
             res[j] = std::sqrt(hn[j] + hn[nb + j]) / (std::fabs(om[j]) * std::sqrt(hn[2 * nb + j] + hn[3 * nb + j]));
             if (j < k) rmax = std::max(rmax, res[j]);
+            if (!(res[j] <= tol)) act.push_back(j);      // soft locking: converged columns get no correction
         }
+        const int nact = (int)act.size();
         if (!(rmax == rmax)) return ctx_fail(c, BDG_EBREAKDOWN, "non-finite residual");
         if (debug_on())
-            fprintf(stderr, "[bdg it %d] omega0=%.12f omega_k=%.12f res_max(k)=%.3e res0=%.3e\n", it, om[0], om[k - 1], rmax,
-                    res[0]);
+            fprintf(stderr, "[bdg it %d] omega0=%.12f omega_k=%.12f res_max(k)=%.3e res0=%.3e active=%d\n", it, om[0],
+                    om[k - 1], rmax, res[0], nact);
         // mixed form: float32 applies of the correction block until the residual reaches
         // refresh_tol or stops decreasing (the float32 rounding of the images sets a floor
         // near eps32 ||H|| / omega); then float64 applies finish the solve
@@ -746,19 +775,14 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             --it;
             continue;
         }
-        if (rmax <= tol) {
+        if (rmax <= tol || nact == 0) {
             // certify with a float64 apply of the current block
             double2* CF = S.col(HSF, S.slotFree);
             double2* CG = S.col(HSG, S.slotFree);
             BDG_TRY(apply64(c, nb, F, G, nh, CF, CG));
             napply64 += nb;
-            hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)CF, nh,
-                               (const double2*)G, nh, (const double*)d_om, Wf, nh);
-            hipLaunchKernelGGL(k_cols_axmy, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)CG, nh,
-                               (const double2*)F, nh, (const double*)d_om, Wg, nh);
-            BDG_TRY(colnorm2(c, nh, nb, Wf, nh, d_n));
-            BDG_TRY(colnorm2(c, nh, nb, Wg, nh, d_n + nb));
-            BDG_TRY(d2h(c, hn.data(), d_n, 2 * nb * sizeof(double)));
+            BDG_TRY(resnorm2(c, nh, nb, CF, G, CG, F, nh, d_om, d_n));
+            BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
             double cmax = 0;
             for (int j = 0; j < nb; ++j) {
                 res[j] = std::sqrt(hn[j] + hn[nb + j]) / (std::fabs(om[j]) * std::sqrt(hn[2 * nb + j] + hn[3 * nb + j]));
@@ -776,23 +800,41 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             --it;
             continue;
         }
-        // preconditioned corrections (the preconditioner's precision only affects the rate)
+        // residual directions of the active columns: f-direction H_+ f - w g, g-direction
+        // H_- g - w f, then the preconditioner (its precision only affects the rate)
+        BDG_TRY(h2d(c, d_act, act.data(), nact * sizeof(int)));
+        hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HF,
+                           (const double2*)G, nh, (const double*)d_om, (const int*)d_act, Wf, nh);
+        hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HG,
+                           (const double2*)F, nh, (const double*)d_om, (const int*)d_act, Wg, nh);
+        BDG_HIP(c, hipGetLastError());
         if (mixed) {
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wf, nh, w32, nh);
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wg, nh,
-                               w32 + (size_t)nb * nh, nh);
-            BDG_TRY(launch_precond<float>(c, 6 * nb, 3, nh, w32, w32, opt.shift));
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const float2*)w32, nh, Wf, nh);
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb,
-                               (const float2*)(w32 + (size_t)nb * nh), nh, Wg, nh);
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wf, nh,
+                               w32, nh);
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wg, nh,
+                               w32 + (size_t)nact * nh, nh);
+            BDG_TRY(launch_precond<float>(c, 6 * nact, 3, nh, w32, w32));
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const float2*)w32, nh,
+                               Wf, nh);
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact,
+                               (const float2*)(w32 + (size_t)nact * nh), nh, Wg, nh);
         } else {
-            BDG_TRY(launch_precond<double>(c, 3 * nb, 3, nh, Wf, Wf, opt.shift));
-            BDG_TRY(launch_precond<double>(c, 3 * nb, 3, nh, Wg, Wg, opt.shift));
+            BDG_TRY(launch_precond<double>(c, 3 * nact, 3, nh, Wf, Wf));
+            BDG_TRY(launch_precond<double>(c, 3 * nact, 3, nh, Wg, Wg));
         }
-        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Wf, nb));
-        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nb));
-        BDG_TRY(unit_columns(c, nh, nb, Wf, nullptr, d_n));
-        BDG_TRY(unit_columns(c, nh, nb, Wg, nullptr, d_n + nb));
+        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Wf, nact));
+        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nact));
+        BDG_TRY(unit_columns(c, nh, nact, Wf, nullptr, d_n));
+        BDG_TRY(unit_columns(c, nh, nact, Wg, nullptr, d_n + nb));
+        // P of the active columns only: gather them (and their images) into the free slot
+        if (S.slotP >= 0 && nact < nb) {
+            for (int a = 0; a < 4; ++a)
+                hipLaunchKernelGGL(k_cols_gather, grid_cols(nh, nact), dim3(256), 0, c->stream, nh,
+                                   (const double2*)S.col(a, S.slotP), nh, (const int*)d_act, S.col(a, S.slotFree),
+                                   nh);
+            BDG_HIP(c, hipGetLastError());
+            std::swap(S.slotP, S.slotFree);
+        }
         BDG_TRY(sync_if());
         t_prec += ms_since(t0);
         auto t1 = now();
@@ -800,30 +842,34 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         double2* HWg = S.col(HSG, S.slotW);
         if (mixed && !force64) {
             float2* wf32 = w32;
-            float2* wg32 = w32 + (size_t)nb * nh;
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wf, nh, wf32, nh);
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const double2*)Wg, nh, wg32, nh);
+            float2* wg32 = w32 + (size_t)nact * nh;
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wf, nh,
+                               wf32, nh);
+            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wg, nh,
+                               wg32, nh);
             BlockRef<const float2> X{wf32, wg32, nh};
-            BlockRef<float2> Y{y32, y32 + (size_t)nb * nh, nh};   // lo: H_- W_g, hi: H_+ W_f
-            BDG_TRY(launch_apply<float>(c, BDG_FORM_FG, 0, nb, X, Y));
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb, (const float2*)y32, nh, HWg, nh);
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nb), dim3(256), 0, c->stream, nh, nb,
-                               (const float2*)(y32 + (size_t)nb * nh), nh, HWf, nh);
-            napply32 += nb;
+            BlockRef<float2> Y{y32, y32 + (size_t)nact * nh, nh};   // lo: H_- W_g, hi: H_+ W_f
+            BDG_TRY(launch_apply<float>(c, BDG_FORM_FG, 0, nact, X, Y));
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const float2*)y32, nh,
+                               HWg, nh);
+            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact,
+                               (const float2*)(y32 + (size_t)nact * nh), nh, HWf, nh);
+            napply32 += nact;
         } else {
-            BDG_TRY(apply64(c, nb, Wf, Wg, nh, HWf, HWg));
-            napply64 += nb;
+            BDG_TRY(apply64(c, nact, Wf, Wg, nh, HWf, HWg));
+            napply64 += nact;
         }
         BDG_TRY(sync_if());
         t_apply += ms_since(t1);
         auto t2 = now();
-        // Gram matrices of [F, W, P]
-        const int ns = S.slotP >= 0 ? 3 : 2;
-        const int mc = ns * nb;
-        Seg sf[3] = {{F, nb}, {Wf, nb}, {S.slotP >= 0 ? S.col(SF, S.slotP) : nullptr, nb}};
-        Seg sg[3] = {{G, nb}, {Wg, nb}, {S.slotP >= 0 ? S.col(SG, S.slotP) : nullptr, nb}};
-        Seg hf[3] = {{HF, nb}, {HWf, nb}, {S.slotP >= 0 ? S.col(HSF, S.slotP) : nullptr, nb}};
-        Seg hg[3] = {{HG, nb}, {HWg, nb}, {S.slotP >= 0 ? S.col(HSG, S.slotP) : nullptr, nb}};
+        // Gram matrices of [F, W, P] (W and P: active columns)
+        const int np = S.slotP >= 0 ? nact : 0;
+        const int ns = np > 0 ? 3 : 2;
+        const int mc = nb + nact + np;
+        Seg sf[3] = {{F, nb}, {Wf, nact}, {np ? S.col(SF, S.slotP) : nullptr, np}};
+        Seg sg[3] = {{G, nb}, {Wg, nact}, {np ? S.col(SG, S.slotP) : nullptr, np}};
+        Seg hf[3] = {{HF, nb}, {HWf, nact}, {np ? S.col(HSF, S.slotP) : nullptr, np}};
+        Seg hg[3] = {{HG, nb}, {HWg, nact}, {np ? S.col(HSG, S.slotP) : nullptr, np}};
         BDG_TRY(grams(sf, sg, hf, hg, ns, mc));
         BDG_TRY(sync_if());
         t_gram += ms_since(t2);
@@ -846,7 +892,8 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         if (rst != BDG_OK) { final_status = rst; break; }
         t_small += ms_since(t3);
         auto t4 = now();
-        // updates: P_new = [W, P] a[nb:], F_new = [F, W, P] a
+        // updates: P_new = [W, P] a[nb:] into the free slot, then F_new = F a[:nb] + P_new
+        // into W's slot (W is no longer read), so no output overlaps an input
         const int dst_P = S.slotFree, dst_F = S.slotW;
         for (int a = 0; a < 4; ++a) {
             const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
@@ -856,7 +903,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         for (int a = 0; a < 4; ++a) {
             const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
             const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
-            BDG_TRY(update(c, nh, seg, ns, nh, coef, mc, nb, 0.0, S.col(a, dst_F), nh));
+            BDG_TRY(update_add(c, nh, seg, 1, nh, coef, mc, nb, 1.0, S.col(a, dst_P), nh, S.col(a, dst_F), nh));
         }
         // rotate slot roles
         const int oldF = S.slotF, oldP = S.slotP;
@@ -904,16 +951,6 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     c->stats[7] = std::min(it, max_iter);
     c->stats[8] = napply64;
     c->stats[9] = napply32;
-    // release
-    small_free(c, w);
-    for (int a = 0; a < 4; ++a) ctx_free(c, S.arr[a]);
-    ctx_free(c, w32);
-    ctx_free(c, y32);
-    ctx_free(c, acoef);
-    ctx_free(c, bcoef);
-    ctx_free(c, dvec);
-    ctx_free(c, D.Nm);
-    ctx_free(c, D.Qg);
     if (final_status == BDG_ENOCONV) return ctx_fail(c, BDG_ENOCONV, "bdg_eigs: iteration limit reached");
     return final_status;
 }
@@ -1145,7 +1182,6 @@ extern "C" bdg_status bdg_eigs_grad(bdg_ctx* c, int k, const double* omega, cons
         g12 = host_dot_re(c, w, nh, yc, yc + nh, &st); BDG_TRY(st);
         g22 = host_dot_re(c, w, nh, yc + nh, yc + nh, &st); BDG_TRY(st);
     }
-    const double shift = 20.0;
     std::vector<double> gbn(k), gbs(k);
     for (int j = 0; j < k; ++j) {
         const double2* uv = (const double2*)UV_dev + (size_t)j * 2 * nh;
@@ -1178,7 +1214,7 @@ extern "C" bdg_status bdg_eigs_grad(bdg_ctx* c, int k, const double* omega, cons
         }
         hipLaunchKernelGGL(k_scale_add, dim3(nblk), dim3(RB2), 0, c->stream, nh, -1.0, (const double2*)ws, qv);
         double2* t = yc;   // reuse
-        BDG_TRY(pcg_hplus(c, w, nh, Q, nq, qv, t, ws, shift, 1e-12, 20000));
+        BDG_TRY(pcg_hplus(c, w, nh, Q, nq, qv, t, ws, 1e-12, 20000));
         hipLaunchKernelGGL(k_scale_add, dim3(nblk), dim3(RB2), 0, c->stream, nh, 1.0, (const double2*)t, y);
         double* dVj = dV_dev + (size_t)j * npts;
         hipLaunchKernelGGL(k_grad_final, dim3(nblk), dim3(RB2), 0, c->stream, npts, (const double*)c->phi,

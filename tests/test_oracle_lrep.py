@@ -13,7 +13,7 @@ from tests import _cases
 def _solve(case, tol=1e-10):
     w, V, r, c = _cases.ground(case)
     X0 = W.start_block(w)
-    out, prob, Nm, Qg = lrep.solve(c, r.phi, w.n, w.L, w.k, X0, tol)
+    out, prob, Nm, Qg = lrep.solve(c, r.phi, w.n, w.L, w.k, X0, tol, V=V, mu=r.mu)
     return w, V, r, c, out, prob, Nm, Qg
 
 
@@ -82,6 +82,27 @@ def test_uniform_2d_matches_dispersion(kind, bs):
     c = bdg.coefficients(phi, mu, V, 20.0, bs)
     w = W.Workload("u", 2, n, L, "zero", 20.0, bs, 0.0)
     X0 = W.start_block(w, nvec=12)
-    out, *_ = lrep.solve(c, phi, n, L, 8, X0, 1e-10)
+    out, *_ = lrep.solve(c, phi, n, L, 8, X0, 1e-10, V=V, mu=mu)
     ref = branch.uniform_spectrum(n, L, 20.0, bs, kind, 8)
     assert np.allclose(out.omega, ref, rtol=1e-12)
+
+
+def test_preconditioner_is_symmetric_positive_and_path_independent():
+    """The kinetic-potential preconditioner is Hermitian positive definite (so it cannot
+    change the fixed points of the iteration), D = 1 where V <= mu, and the kinetic-only
+    preconditioner reaches the same eigenvalues."""
+    w, V, r, c = _cases.ground(_cases.C1)
+    sigma, D = lrep.preconditioner_parameters(V, r.mu)
+    assert sigma == max(0.5 * r.mu[1], 0.5)
+    assert np.all(D <= 1.0) and np.all(D > 0.0)
+    assert np.all(D[V <= r.mu[1]] == 1.0)
+    prob = lrep.LrepProblem(c, w.n, w.L, D)
+    n3 = 3 * V.size
+    T = prob.precond(np.eye(n3, dtype=np.complex128), sigma)
+    assert np.abs(T - T.conj().T).max() < 1e-14 * np.abs(T).max()
+    assert np.linalg.eigvalsh(0.5 * (T + T.conj().T)).min() > 0
+    X0 = W.start_block(w)
+    a, *_ = lrep.solve(c, r.phi, w.n, w.L, w.k, X0, 1e-10, V=V, mu=r.mu)
+    b, *_ = lrep.solve(c, r.phi, w.n, w.L, w.k, X0, 1e-10)
+    assert np.allclose(a.omega, b.omega, rtol=1e-11)
+    assert a.iters < b.iters
