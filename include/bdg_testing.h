@@ -16,8 +16,9 @@ extern "C" {
 #endif
 
 /* C (m1 x m2, ldc) = alpha * A^H B with A: K x m1 (column stride lda), B: K x m2 (ldb), on
- * the FP64 matrix cores with a deterministic split-K reduction.  hermitian = 1 requires
- * A == B and fills C from its upper triangle. */
+ * the FP64 matrix cores with a deterministic split-K reduction.  hermitian = 1 declares
+ * A^H B Hermitian (A == B, or B = M A with M Hermitian): needs m1 == m2, computes the upper
+ * tiles and fills C's lower triangle from them. */
 bdg_status bdg_test_gram(bdg_ctx* ctx, long long K, int m1, int m2, const void* A, long long lda,
                          const void* B, long long ldb, double alpha, void* C, int ldc, int hermitian);
 

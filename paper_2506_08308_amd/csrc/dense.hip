@@ -41,22 +41,54 @@ constexpr int GKC = 16;         // complex rows per LDS chunk (32 real rows)
 constexpr int GKR = 2 * GKC;
 constexpr int GPAD = GKR + 1;   // LDS row pitch in doubles (bank spread)
 
+// Work item -> (split, tile).  Workgroups are dispatched to the 8 XCDs round-robin by linear
+// id, so item w = (id % 8) * per_xcd + id / 8 gives every XCD a contiguous run of items: all
+// tiles of one K-split then run on the same XCD at about the same time and share its L2,
+// and each panel row is fetched from HBM about once.  Hermitian Grams enumerate the upper
+// tiles only.
+__device__ __forceinline__ bool gram_item(long long L, long long per_xcd, long long total, int ntiles, int tn,
+                                          int herm, long long* split, int* ti, int* tj) {
+    const long long w = (L & 7) * per_xcd + (L >> 3);
+    if (w >= total) return false;
+    *split = w / ntiles;
+    int tile = (int)(w % ntiles);
+    if (!herm) {
+        *ti = tile / tn;
+        *tj = tile % tn;
+        return true;
+    }
+    int r = 0;
+    while (tile >= tn - r) {
+        tile -= tn - r;
+        ++r;
+    }
+    *ti = r;
+    *tj = r + tile;
+    return true;
+}
+
 __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegList A, long long lda, SegList B,
-                                              long long ldb, long long kper, int tiles_n, int herm,
+                                              long long ldb, long long kper, int tn, int herm, int same,
+                                              int ntiles, long long total, long long per_xcd,
                                               double2* __restrict__ part) {
     __shared__ double la[GT * GPAD];
     __shared__ double lb[GT * GPAD];
+    long long split;
+    int ti, tj;
+    if (!gram_item(blockIdx.x, per_xcd, total, ntiles, tn, herm, &split, &ti, &tj)) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int tij = blockIdx.x;
-    const int ti = tij / tiles_n, tj = tij % tiles_n;
-    const int split = blockIdx.y;
-    double2* out = part + (long long)split * m1 * m2;
-    if (herm && ti > tj) return;
+    double2* out = part + split * m1 * m2;
+    // diagonal tiles of a Gram of one block with itself (A == B) read one panel
+    const bool diag = same && ti == tj;
+    const double* lbr = diag ? la : lb;
     const int p0 = ti * GT, q0 = tj * GT;
-    const long long k0 = (long long)split * kper;
+    const long long k0 = split * kper;
     long long k1 = k0 + kper;
     if (k1 > K) k1 = K;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // wave sub-tile
+    // the strictly lower sub-tile of a Hermitian diagonal tile is the mirror of the upper one
+    // (filled by the reduction): its wave only helps stage the panels
+    const bool idle = herm && ti == tj && wr > wc;
     d4 accr[2][2], acci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -70,25 +102,34 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
     for (int pass = 0; pass < 4; ++pass) {
         const int col = lc + 16 * pass;
         acol[pass] = (p0 + col < m1) ? seg_col(A, p0 + col, lda) : nullptr;
-        bcol[pass] = (q0 + col < m2) ? seg_col(B, q0 + col, ldb) : nullptr;
+        bcol[pass] = (!diag && q0 + col < m2) ? seg_col(B, q0 + col, ldb) : nullptr;
     }
+    // the next chunk is held in registers while the current one is multiplied
+    double2 ra[4], rb[4];
+    auto gload = [&](long long kc) {
+        const long long kk = kc + lk;
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            ra[pass] = (kk < k1 && acol[pass]) ? acol[pass][kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && bcol[pass]) ? bcol[pass][kk] : double2{0, 0};
+        }
+    };
+    gload(k0);
     for (long long kc = k0; kc < k1; kc += GKC) {
         __syncthreads();
 #pragma unroll
         for (int pass = 0; pass < 4; ++pass) {
             const int col = lc + 16 * pass;
-            const long long kk = kc + lk;
-            double2 va = {0, 0}, vb = {0, 0};
-            if (kk < k1) {
-                if (acol[pass]) va = acol[pass][kk];
-                if (bcol[pass]) vb = bcol[pass][kk];
+            la[col * GPAD + 2 * lk] = ra[pass].x;
+            la[col * GPAD + 2 * lk + 1] = ra[pass].y;
+            if (!diag) {
+                lb[col * GPAD + 2 * lk] = rb[pass].x;
+                lb[col * GPAD + 2 * lk + 1] = rb[pass].y;
             }
-            la[col * GPAD + 2 * lk] = va.x;
-            la[col * GPAD + 2 * lk + 1] = va.y;
-            lb[col * GPAD + 2 * lk] = vb.x;
-            lb[col * GPAD + 2 * lk + 1] = vb.y;
         }
         __syncthreads();
+        if (kc + GKC < k1) gload(kc + GKC);
+        if (idle) continue;
 #pragma unroll
         for (int ks = 0; ks < GKR; ks += 4) {
             const int kr = ks + (lane >> 4);        // real row of this lane
@@ -99,9 +140,9 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int row = (wc + 16 * b + ci) * GPAD;
-                bv[b] = lb[row + kr];
+                bv[b] = lbr[row + kr];
                 // b'[2k] = Im B[k], b'[2k+1] = -Re B[k]
-                bpv[b] = (kr & 1) ? -lb[row + kr - 1] : lb[row + kr + 1];
+                bpv[b] = (kr & 1) ? -lbr[row + kr - 1] : lbr[row + kr + 1];
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -112,6 +153,7 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
                 }
         }
     }
+    if (idle) return;
     // write the partial tile: register r of lane l holds D[4 r + l / 16][l % 16]
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -136,7 +178,9 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)m1 * m2) return;
     int p = (int)(idx % m1), q = (int)(idx / m1);
-    const bool mirror = herm && (p / GT) > (q / GT);
+    // Hermitian: computed blocks are the upper tiles and, inside diagonal tiles, the upper
+    // 32 x 32 sub-tiles; everything below is mirrored
+    const bool mirror = herm && (p / 32) > (q / 32);
     const int ps = mirror ? q : p, qs = mirror ? p : q;
     double sx = 0, sy = 0;
     for (int s = 0; s < nsplit; ++s) {
@@ -160,44 +204,75 @@ template <int CB>
 __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long long lds, int m,
                                                 const double2* __restrict__ Cm, int ldcm, int nb, double beta,
                                                 const double2* Z, long long ldz, double2* Y, long long ldy) {
+    // LDS chunks of UL columns of S (128 rows) and UL rows of Cm (16 CB columns); the next
+    // chunk is held in registers while the MFMAs of the current one run
+    constexpr int UL = 16;
+    constexpr int NC = 16 * CB;
+    constexpr int SP = 129;                          // row pitch of the S chunk (double2)
+    __shared__ double2 lsS[UL * SP];
+    __shared__ double2 lsC[UL * NC];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const long long r0 = ((long long)blockIdx.x * 4 + wave) * 32;
-    const int j0 = blockIdx.y * 16 * CB;
+    const long long R0 = (long long)blockIdx.x * 128;
+    const int j0 = blockIdx.y * NC;
     const int ri = lane & 15, kq = lane >> 4;
+    const int wr = wave * 32;
     d4 accr[2][CB], acci[2][CB];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < CB; ++b) { accr[a][b] = d4{0, 0, 0, 0}; acci[a][b] = d4{0, 0, 0, 0}; }
-    for (int l0 = 0; l0 < m; l0 += 4) {
-        const int l = l0 + kq;                 // column of S for this lane
-        double2 sv[2] = {{0, 0}, {0, 0}};
-        if (l < m) {
-            const double2* col = seg_col(segs, l, lds);
+    constexpr int SPASS = UL * 128 / 256;             // 8 S elements per thread
+    constexpr int CPASS = (UL * NC + 255) / 256;      // <= 5 Cm elements per thread
+    double2 rs[SPASS], rc[CPASS];
+    auto gload = [&](int l0) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const long long row = r0 + 16 * a + ri;
-                if (row < K) sv[a] = col[row];
-            }
-        }
-        double cr[CB], ci[CB];
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int j = j0 + 16 * b + ri;
-            double2 cv = {0, 0};
-            if (l < m && j < nb) cv = Cm[(long long)j * ldcm + l];
-            cr[b] = cv.x;
-            ci[b] = cv.y;
+        for (int u = 0; u < SPASS; ++u) {
+            const int idx = u * 256 + t;
+            const int l = l0 + idx / 128, row = idx % 128;
+            rs[u] = double2{0, 0};
+            if (l < m && R0 + row < K) rs[u] = seg_col(segs, l, lds)[R0 + row];
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int u = 0; u < CPASS; ++u) {
+            const int idx = u * 256 + t;
+            const int l = idx % UL, j = idx / UL;
+            rc[u] = double2{0, 0};
+            if (idx < UL * NC && l0 + l < m && j0 + j < nb) rc[u] = Cm[(long long)(j0 + j) * ldcm + l0 + l];
+        }
+    };
+    gload(0);
+    for (int l0 = 0; l0 < m; l0 += UL) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SPASS; ++u) {
+            const int idx = u * 256 + t;
+            lsS[(idx / 128) * SP + idx % 128] = rs[u];
+        }
+#pragma unroll
+        for (int u = 0; u < CPASS; ++u) {
+            const int idx = u * 256 + t;
+            if (idx < UL * NC) lsC[(idx % UL) * NC + idx / UL] = rc[u];
+        }
+        __syncthreads();
+        if (l0 + UL < m) gload(l0 + UL);
+#pragma unroll
+        for (int ks = 0; ks < UL; ks += 4) {
+            const int l = ks + kq;
+            double2 sv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) sv[a] = lsS[l * SP + wr + 16 * a + ri];
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                accr[a][b] = mfma(sv[a].x, cr[b], accr[a][b]);
-                accr[a][b] = mfma(-sv[a].y, ci[b], accr[a][b]);
-                acci[a][b] = mfma(sv[a].x, ci[b], acci[a][b]);
-                acci[a][b] = mfma(sv[a].y, cr[b], acci[a][b]);
+                const double2 cv = lsC[l * NC + 16 * b + ri];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    accr[a][b] = mfma(sv[a].x, cv.x, accr[a][b]);
+                    accr[a][b] = mfma(-sv[a].y, cv.y, accr[a][b]);
+                    acci[a][b] = mfma(sv[a].x, cv.y, acci[a][b]);
+                    acci[a][b] = mfma(sv[a].y, cv.x, acci[a][b]);
+                }
             }
+        }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -207,7 +282,7 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
             if (j >= nb) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const long long row = r0 + 16 * a + 4 * r + (lane >> 4);
+                const long long row = R0 + wr + 16 * a + 4 * r + (lane >> 4);
                 if (row >= K) continue;
                 double2 v;
                 v.x = accr[a][b][r];
@@ -581,7 +656,8 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         return ctx_fail(c, BDG_EINVAL, "gram: 1..4 segments");
     if (m1 <= 0 || m2 <= 0) return BDG_OK;
     const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
-    const int ntiles = tm * tn;
+    if (hermitian && tm != tn) return ctx_fail(c, BDG_EINVAL, "gram: Hermitian form needs m1 == m2");
+    const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
     long long nsplit = std::max<long long>(1, std::min<long long>((K + 511) / 512, 2048 / ntiles));
     long long kper = (K + nsplit - 1) / nsplit;
     kper = ((kper + GKC - 1) / GKC) * GKC;
@@ -589,9 +665,13 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
     if (nsplit < 1) nsplit = 1;
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
-    dim3 grid((unsigned)ntiles, (unsigned)nsplit);
-    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, c->stream, K, m1, m2, A, lda, B, ldb, kper, tn,
-                       hermitian ? 1 : 0, (double2*)ws);
+    // A == B (same segments, same stride): the diagonal tiles need one panel
+    bool same = hermitian && na == nbs && lda == ldb;
+    for (int i = 0; same && i < na; ++i) same = sa[i].p == sb[i].p && sa[i].ncols == sb[i].ncols;
+    const long long total = nsplit * ntiles;
+    const long long per_xcd = (total + 7) / 8;
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda, B, ldb,
+                       kper, tn, hermitian ? 1 : 0, same ? 1 : 0, ntiles, total, per_xcd, (double2*)ws);
     BDG_HIP(c, hipGetLastError());
     const long long tot = (long long)m1 * m2;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,

@@ -595,10 +595,13 @@ struct EigsOpts {
     double rtol = 1e-12;        // pivoted-Cholesky cut-off (Schur complement of the scaled Gram)
     double eps = 1e-10;         // LU pivot cut-off of the pairing matrix
     double null_tol = 1e-6;     // nullspace candidate test
-    double refresh_tol = 1e-5;  // mixed precision: refresh images once this residual is reached
+    double refresh_tol = 1e-3;  // mixed precision: float64 corrections from this residual on (the
+                                // float32 image floor eps32 ||H|| / omega is ~1e-3 for 3-D traps)
     int refresh_every = 25;     // float64 re-projection and image refresh period (iterations)
-    int stall_iters = 30;       // mixed form: switch to float64 applies after this many
-                                // iterations without halving the residual
+    int stall_iters = 10;       // mixed form: switch to float64 applies after this many
+                                // iterations without halving the residual, or at once when
+                                // it grows past rise_factor times its best value
+    double rise_factor = 4.0;
     double rtol32 = 1e-10;      // cut-offs while images carry float32 rounding
     double eps32 = 1e-8;
 };
@@ -716,6 +719,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     int last_refresh = 0, recoveries = 0, best_it = 0;
     double best_r = 1e300;
     bool switch64 = false;
+    bool armed = false;
     bool converged = false;
     bool refreshed = false;
     int certifications = 0;
@@ -759,10 +763,16 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
                     om[k - 1], rmax, res[0], nact);
         // mixed form: float32 applies of the correction block until the residual reaches
         // refresh_tol or stops decreasing (the float32 rounding of the images sets a floor
-        // near eps32 ||H|| / omega); then float64 applies finish the solve
+        // near eps32 ||H|| / omega, which can lie far above refresh_tol); then float64
+        // applies finish the solve
         if (mixed && !force64) {
-            if (rmax < best_r * 0.5) { best_r = rmax; best_it = it; }
-            if (rmax <= opt.refresh_tol || it - best_it > opt.stall_iters) switch64 = true;
+            // both detectors are armed once the start-up transient is over (residual < 0.1)
+            if (!armed && rmax < 0.1) { armed = true; best_r = rmax; best_it = it; }
+            if (armed) {
+                if (rmax < best_r * 0.5) { best_r = rmax; best_it = it; }
+                if (rmax <= opt.refresh_tol || it - best_it > opt.stall_iters || rmax > opt.rise_factor * best_r)
+                    switch64 = true;
+            }
         }
         const bool want_refresh = switch64 || (it - last_refresh >= opt.refresh_every);
         if (want_refresh) {

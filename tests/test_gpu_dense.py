@@ -21,19 +21,27 @@ def _p(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# herm: 0 general A^H B; 1 Hermitian with B = A; 2 Hermitian with a distinct operand
+# B = D A (D real diagonal), the case of the Rayleigh-Ritz Grams S^H (H S)
 @pytest.mark.parametrize("K,m1,m2,herm", [(37, 5, 7, 0), (1000, 40, 40, 0), (3072, 64, 64, 1), (5000, 80, 120, 0),
-                                          (100000, 240, 240, 1), (70001, 16, 3, 0), (12, 130, 130, 1)])
+                                          (100000, 240, 240, 1), (70001, 16, 3, 0), (12, 130, 130, 1),
+                                          (20000, 144, 144, 2), (4099, 70, 70, 2)])
 def test_gram_matches_numpy(K, m1, m2, herm):
     torch = torch_cuda()
     from paper_2506_08308_amd import _lib
     say(f"gram K={K} {m1}x{m2} herm={herm}")
     ctx = _ctx()
     A = W.random_block((m1, K), seed=1)
-    B = A if herm else W.random_block((m2, K), seed=2)
+    if herm == 1:
+        B = A
+    elif herm == 2:
+        B = A * np.random.default_rng(3).uniform(0.5, 2.0, K)[None, :]
+    else:
+        B = W.random_block((m2, K), seed=2)
     Ad = torch.from_numpy(A).cuda()
-    Bd = Ad if herm else torch.from_numpy(B).cuda()
+    Bd = Ad if herm == 1 else torch.from_numpy(np.ascontiguousarray(B)).cuda()
     C = torch.zeros((m2, m1), dtype=torch.complex128, device="cuda")   # column-major m1 x m2
-    st = ctx._lib.bdg_test_gram(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 0.5, _p(C), m1, herm)
+    st = ctx._lib.bdg_test_gram(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 0.5, _p(C), m1, 1 if herm else 0)
     assert st == _lib.BDG_OK
     got = C.cpu().numpy().T
     ref = 0.5 * (A.conj() @ B.T)
