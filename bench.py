@@ -1,18 +1,25 @@
-"""Benchmark: time to the k lowest BdG eigenpairs on one MI355X, plus the apply roofline.
+"""Benchmark: time to the k lowest BdG eigenpairs on one MI355X, with kernel rooflines.
 
-One step = one full bdg_eigs solve (deflation set-up, subspace iteration with the FFT
-apply, bi-orthogonal Gram-Schmidt, Rayleigh-Ritz, updates, float64 certification) from the
-seed-0 complex-normal start block to residual <= tol for all k wanted pairs.  The ground
-state is computed on the GPU (bdg_ground_state) before the timed region.
+One step = one full bdg_eigs solve (deflation set-up, subspace iteration with the FFT apply,
+bi-orthogonalization, Rayleigh-Ritz, updates, float64 certification) from the seed-0
+complex-normal start block to residual <= tol for all k wanted pairs.  The ground state is
+computed on the GPU (bdg_ground_state) before the timed region; inputs are resident in HBM.
 
-Prints one JSON line (rank 0).  Default workload: 2-D 256^2 box [-12,12]^2, V=(x^2+y^2)/2,
-beta_n=100, beta_s=-2 (ferromagnetic), M=0, k=32, block 48, float64, residual 1e-8.
---workload c3 runs the 3-D 128^3 float32-apply case (k=64, block 80), c3_fp64 its float64
-counterpart, c2_polar the beta_s=+2 run.
+Default workload: the 3-D trap, 128^3 grid on [-8, 8]^3, V = (x^2 + y^2 + 4 z^2)/2,
+beta_n = 400, beta_s = -4, M = 0.1, k = 64, block 80, residual 1e-8, float32-apply mixed
+precision; the float64 solve of the same problem is timed beside it (--no-fp64 skips it).
+
+Prints ONE JSON line.  ``roofline`` is the Gram kernel (k_gram, the largest kernel-time
+share of the solve) against the FP64 matrix peak; ``roofline_apply`` is the BdG apply against
+the HBM peak.  Both are timed live with HIP events on the context stream at the solve's own
+shapes.  ``--kernels-only`` runs just those launches (plus a 1 GiB device copy as the
+traffic reference) for counter collection under rocprofv3.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -31,54 +38,128 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
 
 WORKLOADS = {
-    "c3": W.C3,
-    "c3_fp64": W.C3_FP64,
-    "c2_fm": W.C2_FM,
-    "c2_polar": W.C2_POLAR,
-    "c1": W.C1,
+    "c3": (W.C3, W.C3_FP64),
+    "c3_fp64": (W.C3_FP64, None),
+    "c2_fm": (W.C2_FM, None),
+    "c2_polar": (W.C2_POLAR, None),
+    "c1": (W.C1, None),
 }
+KERNEL_SOURCES = {"gram": "paper_2506_08308_amd/csrc/dense.hip", "apply": "paper_2506_08308_amd/csrc/fft_apply.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def apply_roofline(ctx, w, nvec, reps=10):
-    """Average duration of one block apply (bdg_apply on nvec vectors) with events on the
-    context stream; algorithmic bytes = read X + write Y (6 complex fields per vector) +
-    one read of the 12 coefficient fields."""
+def _prec(w):
+    from paper_2506_08308_amd import Precision
+    return Precision.FP32_APPLY if w.precision == "fp32_apply" else Precision.FP64
+
+
+def _context(w):
+    import torch
+    from paper_2506_08308_amd import BdgContext
+    V = torch.from_numpy(W.potential(w)).to("cuda")
+    return BdgContext(w.dim, w.n, w.L, V, w.beta_n, w.beta_s, w.mass, w.magnetization, _prec(w))
+
+
+def _event_ms(stream, fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _source_hash(key):
+    with open(os.path.join(ROOT, KERNEL_SOURCES[key]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _traffic(key, workload_name):
+    """HBM bytes per launch from the committed counter runs, or None when the kernel source
+    or the workload differs from the one the counters were taken on."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != _source_hash(key) or rec.get("workload") != workload_name:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def gram_launch(ctx, w, reps=5):
+    """One Rayleigh-Ritz Gram of the solve: M_r = S^H (H S) with m = 3 block columns of
+    K = 3 npts complex rows (Hermitian result, distinct operands).  Algorithmic flops:
+    m (m + 1) / 2 complex entries x 8 K."""
+    import torch
+    K, m = 3 * w.npts, 3 * w.block
+    g = torch.Generator(device="cuda").manual_seed(0)
+    A = torch.randn((m, K), dtype=torch.complex128, device="cuda", generator=g)
+    d = torch.rand((K,), dtype=torch.float64, device="cuda", generator=g) + 0.5
+    B = A * d
+    C = torch.empty((m, m), dtype=torch.complex128, device="cuda")
+    lib = ctx._lib
+
+    def run():
+        st = lib.bdg_test_gram(ctx._h, K, m, m, ctypes.c_void_p(A.data_ptr()), K, ctypes.c_void_p(B.data_ptr()),
+                               K, 1.0, ctypes.c_void_p(C.data_ptr()), m, 1)
+        if st != 0:
+            raise RuntimeError(f"bdg_test_gram failed with status {st}")
+
+    ms = _event_ms(ctx.stream, run, reps)
+    flops = 4.0 * K * m * (m + 1)
+    del A, B, C, d
+    torch.cuda.empty_cache()
+    return ms, flops
+
+
+def apply_launch(ctx, w, reps=10):
+    """bdg_apply on the full block (the correction block's apply in the solve).  Algorithmic
+    bytes: read X and write Y (6 complex fields per vector) plus one read of the 12
+    coefficient fields."""
     import torch
     from paper_2506_08308_amd import Form
     dt = ctx.vector_dtype()
-    X = torch.randn((nvec, 6) + w.shape, dtype=dt, device="cuda")
+    X = torch.randn((w.block, 6) + w.shape, dtype=dt, device="cuda")
     Y = torch.empty_like(X)
-    s = ctx.stream
-    for _ in range(2):
-        ctx.apply(X, Form.FG, out=Y)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        ctx.apply(X, Form.FG, out=Y)
-    e1.record(s)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms = _event_ms(ctx.stream, lambda: ctx.apply(X, Form.FG, out=Y), reps)
     csize = 8 if dt == torch.complex64 else 16
-    rsize = csize // 2
-    bytes_alg = nvec * 2 * 6 * w.npts * csize + 12 * w.npts * rsize
+    nbytes = w.block * 2 * 6 * w.npts * csize + 12 * w.npts * (csize // 2)
     del X, Y
-    return ms, bytes_alg
+    torch.cuda.empty_cache()
+    return ms, nbytes
+
+
+def copy_reference(reps=3):
+    """A plain device copy of 1 GiB (the traffic-counter reference)."""
+    import torch
+    x = torch.empty((1 << 27,), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    ms = _event_ms(torch.cuda.current_stream(), lambda: y.copy_(x), reps)
+    del x, y
+    return ms
 
 
 def cpu_baseline(w, gpu_iters, budget_s=20.0):
-    """The CPU oracle's subspace iteration (numpy FP64, host cores) on a bounded sample:
-    a fixed number of iterations of the same algorithm on the workload (scaled to a grid the
-    host can hold when the full block does not fit), extrapolated to the GPU's iteration
-    count and, when scaled, by DOF log DOF."""
-    import oracle
+    """The CPU oracle's subspace iteration (numpy FP64 on the host cores) on a bounded sample:
+    a few iterations of the same algorithm on the same problem at a grid the host holds
+    (each axis halved until 14 FP64 blocks fit in 4 GB), extrapolated to the GPU's iteration
+    count and by DOF log DOF to the full grid."""
     from oracle import bdg, groundstate as gs, lrep
-    cores = os.cpu_count()
-    full_bytes = 14 * w.block * 6 * w.npts * 16
+    try:
+        import threadpoolctl
+        blas_threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count()
     n_s = w.n[0]
     while n_s > 8 and 14 * w.block * 6 * (n_s ** w.dim) * 16 > 4e9:
         n_s //= 2
@@ -92,15 +173,11 @@ def cpu_baseline(w, gpu_iters, budget_s=20.0):
     prob = lrep.LrepProblem(coef, ws.n, ws.L, D)
     Nm, Qg = lrep.deflation_sets(prob, r.phi, cg_tol=1e-10, sigma=sigma)
     X0 = W.start_block(ws)
-    # time iterations of the subspace iteration (set-up excluded)
-    iters = 0
-    t1 = time.time()
-    per_it = None
+    per_it, iters = None, 0
     for n_it in (2, 4, 8):
         t1 = time.time()
         lrep.lrep_eigs(prob, ws.k, X0, 1e-30, max_iter=n_it, Nm=Nm, Qg=Qg, sigma=sigma)
-        dt = time.time() - t1
-        per_it = dt / n_it
+        per_it = (time.time() - t1) / n_it
         iters = n_it
         if time.time() - t0 > budget_s / 2:
             break
@@ -108,62 +185,102 @@ def cpu_baseline(w, gpu_iters, budget_s=20.0):
     if ws is not w:
         d_full, d_s = 6 * w.npts, 6 * ws.npts
         scale = (d_full * np.log2(d_full)) / (d_s * np.log2(d_s))
-    value = per_it * gpu_iters * scale
-    return {"value": value, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": f"{iters} iterations of the oracle subspace iteration at grid {ws.n} (block {ws.block}), "
-                      f"{per_it:.3f} s/iteration, x {gpu_iters} GPU iterations"
-                      + (f", x {scale:.1f} (DOF log DOF scaling to {w.n})" if ws is not w else "")}
+    return {"value": round(per_it * gpu_iters * scale, 1), "unit": "s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": f"{iters} iterations of the oracle subspace iteration (numpy FP64; BLAS on {blas_threads} "
+                      f"threads, numpy FFT on one) at grid {list(ws.n)}, block {ws.block}: {per_it:.3f} s per "
+                      f"iteration, x {gpu_iters} GPU iterations"
+                      + (f", x {scale:.1f} (DOF log DOF from {list(ws.n)} to {list(w.n)})" if ws is not w else "")}
+
+
+def solve(w, X0, steps, warmup, max_iter):
+    import torch
+    ctx = _context(w)
+    t = time.time()
+    _, mu, gres, gits = ctx.ground_state(tol=w.gs_tol, max_iter=200000)
+    torch.cuda.synchronize()
+    gs_s = time.time() - t
+    log(f"[{w.name}] ground state: {gits} iterations, residual {gres:.2e}, mu {mu}, {gs_s:.2f} s")
+    for i in range(warmup):
+        out = ctx.eigs(w.k, w.block, tol=w.tol, max_iter=max_iter, X0=X0, want_vectors=False)
+        log(f"[{w.name}] warmup {i}: {out['iters']} iterations")
+    times, out = [], None
+    for i in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = ctx.eigs(w.k, w.block, tol=w.tol, max_iter=max_iter, X0=X0, want_vectors=False)
+        torch.cuda.synchronize()
+        times.append(time.time() - t0)
+        log(f"[{w.name}] step {i}: {times[-1]:.3f} s, {out['iters']} iterations, stats {ctx.stats()}")
+    return ctx, out, times, gs_s
+
+
+def kernels_only(w):
+    """Only the roofline launches and the copy reference (for rocprofv3 counter runs)."""
+    import torch
+    ctx = _context(w)
+    ctx.set_ground_state(torch.from_numpy(W.initial_spinor(w)).to("cuda"), [1.0, 1.0, 1.0])
+    c_ms = copy_reference()
+    g_ms, _ = gram_launch(ctx, w, reps=2)
+    a_ms, _ = apply_launch(ctx, w, reps=2)
+    log(f"copy 1 GiB {c_ms:.3f} ms, gram {g_ms:.3f} ms, apply {a_ms:.3f} ms")
+    ctx.close()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2_fm", choices=sorted(WORKLOADS))
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 solve timed beside the mixed one")
+    ap.add_argument("--kernels-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (multi-GPU sharding is designed, not built); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; the multi-GPU sharding is designed, not built. "
+              "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_2506_08308_amd import BdgContext, Precision
-
-    w = WORKLOADS[args.workload]
-    prec = Precision.FP32_APPLY if w.precision == "fp32_apply" else Precision.FP64
-    V = torch.from_numpy(W.potential(w)).to("cuda")
-    ctx = BdgContext(w.dim, w.n, w.L, V, w.beta_n, w.beta_s, w.mass, w.magnetization, prec)
-    t = time.time()
-    phi, mu, gres, gits = ctx.ground_state(tol=w.gs_tol, max_iter=200000)
-    torch.cuda.synchronize()
-    gs_s = time.time() - t
-    log(f"ground state: {gits} iterations, residual {gres:.2e}, mu {mu}, {gs_s:.2f} s")
+    w, w64 = WORKLOADS[args.workload]
+    if args.no_fp64:
+        w64 = None
+    if args.kernels_only:
+        kernels_only(w)
+        return
     X0 = torch.from_numpy(W.start_block(w)).to("cuda")
-    out = None
-    for i in range(args.warmup):
-        out = ctx.eigs(w.k, w.block, tol=w.tol, max_iter=args.max_iter, X0=X0, want_vectors=False)
-        log(f"warmup {i}: iters {out['iters']} stats {ctx.stats()}")
-    torch.cuda.synchronize()
-    times = []
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.time()
-        out = ctx.eigs(w.k, w.block, tol=w.tol, max_iter=args.max_iter, X0=X0, want_vectors=False)
-        torch.cuda.synchronize()
-        times.append(time.time() - t0)
-        log(f"step {i}: {times[-1]:.3f} s iters {out['iters']} stats {ctx.stats()}")
+    ctx, out, times, gs_s = solve(w, X0, args.steps, args.warmup, args.max_iter)
     st = ctx.stats()
     ms = 1000.0 * float(np.mean(times))
-    # apply roofline on the full block
-    a_ms, a_bytes = apply_roofline(ctx, w, w.block)
-    achieved = a_bytes / (a_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"bdg_apply (5 fused FFT/coupling passes) on {w.block} vectors",
-            "ms_per_launch": round(a_ms, 4), "algorithmic_bytes": a_bytes}
+    g_ms, g_flops = gram_launch(ctx, w)
+    a_ms, a_bytes = apply_launch(ctx, w)
+    ctx.close()
+    g_tfs = g_flops / (g_ms * 1e-3) / 1e12
+    a_gbs = a_bytes / (a_ms * 1e-3) / 1e9
+    roof = {"bound": "mfma", "achieved": round(g_tfs, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(g_tfs / FP64_MFMA_PEAK_TFS, 4), "traffic": _traffic("gram", w.name),
+            "kernel": f"k_gram: Rayleigh-Ritz Gram S^H (H S), {3 * w.block} columns x {3 * w.npts} rows, FP64 MFMA",
+            "ms_per_launch": round(g_ms, 3), "algorithmic_flops": g_flops}
+    roof_apply = {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(a_gbs / HBM_PEAK_GBS, 4), "traffic": _traffic("apply", w.name),
+                  "kernel": f"bdg_apply on {w.block} vectors ({'complex64' if _prec(w) == 1 else 'complex128'})",
+                  "ms_per_launch": round(a_ms, 3), "algorithmic_bytes": a_bytes}
+    config = {"workload": w.name, "grid": list(w.n), "box": [-w.L[0], w.L[0]], "potential": w.potential,
+              "beta_n": w.beta_n, "beta_s": w.beta_s, "magnetization": w.magnetization, "k": w.k,
+              "block": w.block, "tol": w.tol, "precision": w.precision, "iters": int(st["iters"]),
+              "applies_fp64": int(st["applies_fp64"]), "applies_fp32": int(st["applies_fp32"]),
+              "phase_ms": {k: round(st[k], 1) for k in ("apply_ms", "precond_ms", "gram_ms", "small_ms",
+                                                       "update_ms", "setup_ms")},
+              "ground_state_s": round(gs_s, 3), "omega_first": [round(v, 12) for v in out["omega"][:4]],
+              "max_residual": max(out["residual"])}
+    if w64 is not None:
+        ctx64, out64, t64, _ = solve(w64, X0, 1, 0, args.max_iter)
+        st64 = ctx64.stats()
+        ctx64.close()
+        rel = max(abs(a - b) / abs(b) for a, b in zip(out["omega"], out64["omega"]))
+        config["fp64_solve"] = {"s": round(t64[0], 3), "iters": int(st64["iters"]),
+                                "max_rel_omega_diff_vs_mixed": rel}
     line = {
         "metric": METRIC,
         "value": round(ms / 1000.0, 4),
@@ -175,18 +292,11 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "c64-apply/f64" if prec == Precision.FP32_APPLY else "f64",
+        "dtype": "c64-apply/f64" if w.precision == "fp32_apply" else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "grid": list(w.n), "box": [-w.L[0], w.L[0]], "k": w.k,
-                   "block": w.block, "tol": w.tol, "beta_n": w.beta_n, "beta_s": w.beta_s,
-                   "magnetization": w.magnetization, "potential": w.potential,
-                   "iters": int(st["iters"]), "applies_fp64": int(st["applies_fp64"]),
-                   "applies_fp32": int(st["applies_fp32"]),
-                   "phase_ms": {k: round(st[k], 1) for k in ("apply_ms", "precond_ms", "gram_ms", "small_ms",
-                                                            "update_ms", "setup_ms")},
-                   "ground_state_s": round(gs_s, 3), "omega_first": out["omega"][:4],
-                   "max_residual": max(out["residual"])},
+        "config": config,
         "roofline": roof,
+        "roofline_apply": roof_apply,
     }
     if not args.no_cpu_baseline:
         try:
@@ -194,7 +304,6 @@ def main():
         except Exception as e:  # report, do not hide
             line["cpu_baseline"] = {"value": None, "error": repr(e)}
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":
