@@ -60,6 +60,36 @@ __global__ void k_cols_axmy_idx(long long K, const double2* __restrict__ X, cons
     }
 }
 
+// scales of the basis columns [F (nb), W, P]: 1 for F, 1 / ||column|| after it (0 for a
+// zero column); v holds the squared norms from position nb on
+__global__ void k_make_scales(int m, int nb, double* v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    if (i < nb) {
+        v[i] = 1.0;
+    } else {
+        const double a = v[i];
+        v[i] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+    }
+}
+
+// A(i, j) *= sl[i] * sr[j] (m x m, ld lda)
+__global__ void k_small_scale2(int m, double2* A, int lda, const double* __restrict__ sl, const double* __restrict__ sr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= m) return;
+    const double f = sl[i] * sr[j];
+    double2 a = A[(long long)j * lda + i];
+    A[(long long)j * lda + i] = cmk<double2>(a.x * f, a.y * f);
+}
+
+// A(i, j) *= s[i] (m x n, ld lda)
+__global__ void k_small_scale_rows(int m, double2* A, int lda, const double* __restrict__ s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= m) return;
+    double2 a = A[(long long)j * lda + i];
+    A[(long long)j * lda + i] = cmk<double2>(a.x * s[i], a.y * s[i]);
+}
+
 // Y(:, t) = X(:, idx[t]) for t < gridDim.y; X and Y must not overlap
 __global__ void k_cols_gather(long long K, const double2* __restrict__ X, long long ldx, const int* __restrict__ idx,
                               double2* __restrict__ Y, long long ldy) {
@@ -390,16 +420,6 @@ bdg_status project_out(bdg_ctx* c, Small& w, long long nh, const double2* Q, int
     return update(c, nh, &s, 1, nh, Cq, q, ncols, 1.0, X, nh);
 }
 
-bdg_status unit_columns(bdg_ctx* c, long long nh, int ncols, double2* X, double2* HX, double* nrm_dev) {
-    BDG_TRY(colnorm2(c, nh, ncols, X, nh, nrm_dev));
-    hipLaunchKernelGGL(k_cols_scale, grid_cols(nh, ncols), dim3(256), 0, c->stream, nh, ncols, X, nh,
-                       (const double*)nrm_dev, 1);
-    if (HX)
-        hipLaunchKernelGGL(k_cols_scale, grid_cols(nh, ncols), dim3(256), 0, c->stream, nh, ncols, HX, nh,
-                           (const double*)nrm_dev, 1);
-    return hip_check(c, hipGetLastError(), "unit_columns");
-}
-
 // orthonormal basis (nh x r) of the columns of X (nh x p) into Out; rank by rtol on the Gram
 bdg_status orthonormalize(bdg_ctx* c, Small& w, long long nh, const double2* X, int p, double2* Out, double rtol,
                           int* r_out) {
@@ -623,6 +643,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     double2* bcoef = nullptr;
     double* dvec = nullptr;
     int* d_act = nullptr;
+    double* d_scl = nullptr;
     Deflation D;
     // every exit path releases the workspace
     auto release = defer([&] {
@@ -634,6 +655,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         ctx_free(c, bcoef);
         ctx_free(c, dvec);
         ctx_free(c, d_act);
+        ctx_free(c, d_scl);
         ctx_free(c, D.Nm);
         ctx_free(c, D.Qg);
     });
@@ -649,6 +671,9 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     BDG_TRY(ctx_alloc(c, (void**)&bcoef, (size_t)m * nb * sizeof(double2)));
     BDG_TRY(ctx_alloc(c, (void**)&dvec, 8 * (size_t)nb * sizeof(double)));
     BDG_TRY(ctx_alloc(c, (void**)&d_act, (size_t)nb * sizeof(int)));
+    BDG_TRY(ctx_alloc(c, (void**)&d_scl, 2 * (size_t)m * sizeof(double)));
+    double* d_sf = d_scl;          // column scales of S_f = [F, W_f, P_f]
+    double* d_sg = d_scl + m;      // and of S_g
     double* d_om = dvec;
     double* d_n = dvec + nb;      // 4 nb norms
     // ------------------------------------------------------------------ deflation
@@ -834,8 +859,10 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         }
         BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Wf, nact));
         BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nact));
-        BDG_TRY(unit_columns(c, nh, nact, Wf, nullptr, d_n));
-        BDG_TRY(unit_columns(c, nh, nact, Wg, nullptr, d_n + nb));
+        // W and P keep their raw scale in memory; unit columns are applied to the Gram
+        // matrices and to the coefficient rows instead (H (S diag(s)) = (H S) diag(s))
+        BDG_TRY(colnorm2(c, nh, nact, Wf, nh, d_sf + nb));
+        BDG_TRY(colnorm2(c, nh, nact, Wg, nh, d_sg + nb));
         // P of the active columns only: gather them (and their images) into the free slot
         if (S.slotP >= 0 && nact < nb) {
             for (int a = 0; a < 4; ++a)
@@ -881,6 +908,27 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         Seg hf[3] = {{HF, nb}, {HWf, nact}, {np ? S.col(HSF, S.slotP) : nullptr, np}};
         Seg hg[3] = {{HG, nb}, {HWg, nact}, {np ? S.col(HSG, S.slotP) : nullptr, np}};
         BDG_TRY(grams(sf, sg, hf, hg, ns, mc));
+        if (np) {
+            BDG_TRY(colnorm2(c, nh, np, S.col(SF, S.slotP), nh, d_sf + nb + nact));
+            BDG_TRY(colnorm2(c, nh, np, S.col(SG, S.slotP), nh, d_sg + nb + nact));
+        }
+        {
+            const dim3 g1((unsigned)((mc + 127) / 128));
+            hipLaunchKernelGGL(k_make_scales, g1, dim3(128), 0, c->stream, mc, nb, d_sf);
+            hipLaunchKernelGGL(k_make_scales, g1, dim3(128), 0, c->stream, mc, nb, d_sg);
+            const dim3 g2((unsigned)((mc + 127) / 128), (unsigned)mc);
+            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Gf, mc, (const double*)d_sf,
+                               (const double*)d_sf);
+            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Gg, mc, (const double*)d_sg,
+                               (const double*)d_sg);
+            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Br, mc, (const double*)d_sg,
+                               (const double*)d_sf);
+            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Mr, mc, (const double*)d_sf,
+                               (const double*)d_sf);
+            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Kr, mc, (const double*)d_sg,
+                               (const double*)d_sg);
+            BDG_HIP(c, hipGetLastError());
+        }
         BDG_TRY(sync_if());
         t_gram += ms_since(t2);
         auto t3 = now();
@@ -900,6 +948,13 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             continue;
         }
         if (rst != BDG_OK) { final_status = rst; break; }
+        {
+            // coefficients of the raw (unscaled) columns
+            const dim3 g2((unsigned)((mc + 127) / 128), (unsigned)nb);
+            hipLaunchKernelGGL(k_small_scale_rows, g2, dim3(128), 0, c->stream, mc, acoef, mc, (const double*)d_sf);
+            hipLaunchKernelGGL(k_small_scale_rows, g2, dim3(128), 0, c->stream, mc, bcoef, mc, (const double*)d_sg);
+            BDG_HIP(c, hipGetLastError());
+        }
         t_small += ms_since(t3);
         auto t4 = now();
         // updates: P_new = [W, P] a[nb:] into the free slot, then F_new = F a[:nb] + P_new
@@ -922,9 +977,6 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         S.slotW = oldF;
         S.slotFree = (oldP >= 0) ? oldP : S.slotFree2;
         S.slotFree2 = -1;
-        // unit columns of P (and images, same factor)
-        BDG_TRY(unit_columns(c, nh, nb, S.col(SF, S.slotP), S.col(HSF, S.slotP), d_n));
-        BDG_TRY(unit_columns(c, nh, nb, S.col(SG, S.slotP), S.col(HSG, S.slotP), d_n + nb));
         BDG_TRY(sync_if());
         t_upd += ms_since(t4);
     }
