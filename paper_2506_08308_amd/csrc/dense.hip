@@ -371,10 +371,9 @@ __global__ void __launch_bounds__(1024) k_small_cholesky(int m, double2* A, int 
 }
 
 // One-sided Jacobi SVD by column blocks (round-robin ordering of blocks, complex rotations).
-// A launch processes one round: workgroup b takes a pair of blocks of w columns, stages their
-// columns of G (rows) and V (m) in LDS, runs one sweep over all pairs of its 2w columns and
-// writes them back.  Rotations of columns whose squared norm is below negl (1e-30 ||G||_F^2)
-// are skipped: such columns are numerically zero.
+// A launch processes one round: workgroup b takes a pair of blocks of W columns and runs one
+// sweep over all pairs of its 2W columns (k_bjacobi_round_g).  Rotations of columns whose
+// squared norm is below negl (1e-30 ||G||_F^2) are skipped: such columns are numerically zero.
 __global__ void k_identity_frob(int rows, int m, const double2* __restrict__ G, int ldg, double2* V, int ldv,
                                 double* frob2, int* counter) {
     __shared__ double red[16];
@@ -400,112 +399,136 @@ __global__ void k_identity_frob(int rows, int m, const double2* __restrict__ G, 
 
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-__global__ void __launch_bounds__(256) k_bjacobi_round(int rows, int m, double2* G, int ldg, double2* V, int ldv,
-                                                       int w, int nblk, int rnd, const double* __restrict__ frob2,
-                                                       int* rotations) {
+// One round of the block one-sided Jacobi: the workgroup stages its 2W columns of G, forms their
+// Gram matrix A = C^H C, runs the sweep over all pairs of its 2W columns on A alone
+// (A <- R^H A R per disjoint pair, two LDS phases per step) while accumulating the unitary
+// J = prod R, and applies J once to the 2W columns of G and V.  The rotations are those of
+// the column form (they are computed from the same inner products); the per-step work is two
+// LDS entries per thread instead of a pass over all rows.
+template <int W>
+__global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double2* G, int ldg, double2* V, int ldv,
+                                                         int nblk, int rnd, const double* __restrict__ frob2,
+                                                         int* rotations) {
+    constexpr int N2 = 2 * W, PA = N2 + 1;
     extern __shared__ double2 sm[];
+    __shared__ double prm[W][4];
+    __shared__ int pact[W];
     __shared__ int rot_any;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (nblk - 1)) + 1; };
     const int P = player(blockIdx.x), Q = player(nblk - 1 - blockIdx.x);
-    const int c0[2] = {P * w, Q * w};
+    const int c0[2] = {P * W, Q * W};
     int nc[2];
     for (int h = 0; h < 2; ++h) {
         const int lim = m - c0[h];
-        nc[h] = lim <= 0 ? 0 : (lim < w ? lim : w);
+        nc[h] = lim <= 0 ? 0 : (lim < W ? lim : W);
     }
-    double2* lg = sm;                          // 2w columns of G, pitch rows
-    double2* lv = sm + (size_t)2 * w * rows;   // 2w columns of V, pitch m
+    auto valid = [&](int k) { return (k % W) < nc[k / W]; };
+    auto colidx = [&](int k) { return c0[k / W] + (k % W); };
+    const int pg = rows | 1;
+    double2* lg = sm;                          // N2 columns of G, pitch pg
+    double2* A = lg + (size_t)N2 * pg;         // N2 x N2, pitch PA
+    double2* J = A + N2 * PA;                  // N2 x N2, pitch PA
     if (t == 0) rot_any = 0;
-    // stage (flattened, eight independent loads in flight per thread)
-    {
-        const int ng = 2 * w * rows, nv = 2 * w * m, tot = ng + nv;
-        for (int e0 = t; e0 < tot; e0 += 8 * blockDim.x) {
-            double2 buf[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * blockDim.x;
-                buf[u] = mkc(0.0, 0.0);
-                if (e < tot) {
-                    const bool isg = e < ng;
-                    const int ee = isg ? e : e - ng, len = isg ? rows : m;
-                    const int cidx = ee / len, i = ee % len, h = cidx / w, cc = cidx % w;
-                    if (cc < nc[h]) {
-                        const long long col = c0[h] + cc;
-                        buf[u] = isg ? G[col * ldg + i] : V[col * ldv + i];
-                    }
-                }
+    for (int e = t; e < N2 * rows; e += nt) {
+        const int k = e / rows, i = e % rows;
+        lg[k * pg + i] = valid(k) ? G[(long long)colidx(k) * ldg + i] : mkc(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = t; e < N2 * N2; e += nt) {
+        const int r = e % N2, c = e / N2;
+        if (r <= c) {
+            double sx = 0, sy = 0;
+            for (int i = 0; i < rows; ++i) {
+                const double2 a = lg[r * pg + i], b = lg[c * pg + i];
+                sx += a.x * b.x + a.y * b.y;
+                sy += a.x * b.y - a.y * b.x;
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * blockDim.x;
-                if (e < tot) sm[e] = buf[u];
-            }
+            A[c * PA + r] = mkc(sx, sy);            // conj(c_r) . c_c
+            if (r != c) A[r * PA + c] = mkc(sx, -sy);
         }
+        J[c * PA + r] = mkc(r == c ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
     const double negl = 1e-30 * (*frob2);
     const double tol = 1e-15, conv = 1e-13;
-    const int tpp = blockDim.x / w;            // threads per column pair (w pairs per inner round)
+    const int tpp = nt / W;
     const int pair = t / tpp, sub = t % tpp;
-    const int n2 = 2 * w;
-    for (int r2 = 0; r2 < n2 - 1; ++r2) {
-        auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (n2 - 1)) + 1; };
-        int p = pl(pair), q = pl(n2 - 1 - pair);
+    for (int r2 = 0; r2 < N2 - 1; ++r2) {
+        auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (N2 - 1)) + 1; };
+        int p = pl(pair), q = pl(N2 - 1 - pair);
         if (p > q) { const int tmp = p; p = q; q = tmp; }
-        const bool valid = (p % w) < nc[p / w] && (q % w) < nc[q / w];
-        double al = 0, be = 0, gx = 0, gy = 0;
-        if (valid) {
-            for (int i = sub; i < rows; i += tpp) {
-                const double2 a = lg[p * rows + i], b = lg[q * rows + i];
-                al += a.x * a.x + a.y * a.y;
-                be += b.x * b.x + b.y * b.y;
-                gx += a.x * b.x + a.y * b.y;
-                gy += a.x * b.y - a.y * b.x;
+        if (sub == 0 && pair < W) {
+            int act = 0;
+            if (valid(p) && valid(q)) {
+                const double al = A[p * PA + p].x, be = A[q * PA + q].x;
+                const double2 gm = A[q * PA + p];
+                const double g = sqrt(gm.x * gm.x + gm.y * gm.y);
+                if (g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
+                    if (g > conv * sqrt(al * be)) rot_any = 1;
+                    const double zeta = (be - al) / (2.0 * g);
+                    const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
+                                                         : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                    prm[pair][0] = cs;
+                    prm[pair][1] = cs * tt;
+                    prm[pair][2] = gm.x / g;     // e = conj(gamma) / |gamma|
+                    prm[pair][3] = -gm.y / g;
+                    act = 1;
+                }
+            }
+            pact[pair] = act;
+        }
+        __syncthreads();
+        const bool act = pair < W && pact[pair];
+        double cs = 0, sn = 0, ex = 0, ey = 0;
+        if (act) { cs = prm[pair][0]; sn = prm[pair][1]; ex = prm[pair][2]; ey = prm[pair][3]; }
+        if (act) {
+            // columns p, q of A and J: [a, b] <- [cs a - sn e b, sn a + cs e b]
+            for (int i = sub; i < N2; i += tpp) {
+                double2 a = A[p * PA + i], b = A[q * PA + i];
+                double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
+                A[p * PA + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                A[q * PA + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+                a = J[p * PA + i];
+                b = J[q * PA + i];
+                eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
+                J[p * PA + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                J[q * PA + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
             }
         }
-        for (int off = 1; off < tpp; off <<= 1) {
-            al += __shfl_xor(al, off);
-            be += __shfl_xor(be, off);
-            gx += __shfl_xor(gx, off);
-            gy += __shfl_xor(gy, off);
-        }
-        const double g = sqrt(gx * gx + gy * gy);
-        if (valid && g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
-            // a sweep counts as converged once every pair is below conv (quadratic convergence:
-            // one more sweep would take the off-diagonal to ~conv^2)
-            if (sub == 0 && g > conv * sqrt(al * be)) rot_any = 1;
-            const double zeta = (be - al) / (2.0 * g);
-            const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
-                                                 : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-            const double ex = gx / g, ey = -gy / g;     // e^{-i theta}, gamma = |gamma| e^{i theta}
-            for (int i = sub; i < rows; i += tpp) {
-                const double2 a = lg[p * rows + i], b = lg[q * rows + i];
-                const double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
-                lg[p * rows + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                lg[q * rows + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
-            }
-            for (int i = sub; i < m; i += tpp) {
-                const double2 a = lv[p * m + i], b = lv[q * m + i];
-                const double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
-                lv[p * m + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                lv[q * m + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
+        __syncthreads();
+        if (act) {
+            // rows p, q of A: [a; b] <- [cs a - sn conj(e) b; sn a + cs conj(e) b]
+            for (int j = sub; j < N2; j += tpp) {
+                const double2 a = A[j * PA + p], b = A[j * PA + q];
+                const double2 eb = mkc(ex * b.x + ey * b.y, ex * b.y - ey * b.x);
+                A[j * PA + p] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
+                A[j * PA + q] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
             }
         }
         __syncthreads();
     }
-    // write back
-    {
-        const int ng = 2 * w * rows, nv = 2 * w * m, tot = ng + nv;
-        for (int e = t; e < tot; e += blockDim.x) {
-            const bool isg = e < ng;
-            const int ee = isg ? e : e - ng, len = isg ? rows : m;
-            const int cidx = ee / len, i = ee % len, h = cidx / w, cc = cidx % w;
-            if (cc >= nc[h]) continue;
-            const long long col = c0[h] + cc;
-            if (isg) G[col * ldg + i] = sm[e];
-            else V[col * ldv + i] = sm[e];
+    // [G; V] columns <- [G; V] columns J (row-local: each thread owns whole rows)
+    for (int i = t; i < rows + m; i += nt) {
+        const bool isg = i < rows;
+        const int ii = isg ? i : i - rows;
+        double2 x[N2];
+#pragma unroll
+        for (int k = 0; k < N2; ++k)
+            x[k] = isg ? lg[k * pg + ii] : (valid(k) ? V[(long long)colidx(k) * ldv + ii] : mkc(0.0, 0.0));
+#pragma unroll
+        for (int c = 0; c < N2; ++c) {
+            if (!valid(c)) continue;
+            double sx = 0, sy = 0;
+#pragma unroll
+            for (int k = 0; k < N2; ++k) {
+                const double2 jj = J[c * PA + k];
+                sx += x[k].x * jj.x - x[k].y * jj.y;
+                sy += x[k].x * jj.y + x[k].y * jj.x;
+            }
+            if (isg) G[(long long)colidx(c) * ldg + ii] = mkc(sx, sy);
+            else V[(long long)colidx(c) * ldv + ii] = mkc(sx, sy);
         }
     }
     if (t == 0 && rot_any) atomicAdd(rotations, 1);
@@ -737,9 +760,16 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
             v = 64 * 1024;
         lds_limit = v;
     }
-    int w = 16;
-    while (w > 4 && (size_t)2 * w * (rows + m) * sizeof(double2) + 64 > (size_t)lds_limit) w >>= 1;
-    if ((size_t)2 * w * (rows + m) * sizeof(double2) + 64 > (size_t)lds_limit)
+    // block width W: the 2W staged columns of G and the two 2W x 2W matrices (Gram and the
+    // accumulated rotation) must fit in the workgroup's LDS
+    auto lds_need = [&](int w) {
+        return ((size_t)2 * w * (size_t)(rows | 1) + (size_t)2 * (2 * w) * (2 * w + 1)) * sizeof(double2) + 1024;
+    };
+    // W = 8 measured fastest on the 2-D and 3-D solves (more workgroups per round, shorter
+    // inner sweeps); 16 and 4 are kept for the LDS fallback
+    int w = 8;
+    while (w > 4 && lds_need(w) > (size_t)lds_limit) w >>= 1;
+    if (lds_need(w) > (size_t)lds_limit)
         return ctx_fail(c, BDG_EINVAL, "small_svd: matrix too large for the LDS-staged Jacobi");
     int nblk = (m + w - 1) / w;
     if (nblk < 2) nblk = 2;
@@ -751,13 +781,23 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
     hipLaunchKernelGGL(k_identity_frob, dim3(1), dim3(1024), 0, c->stream, rows, m, (const double2*)G, ldg, V, ldv,
                        frob2, counter);
     BDG_HIP(c, hipGetLastError());
-    const size_t lds = (size_t)2 * w * (rows + m) * sizeof(double2);
-    BDG_HIP(c, hipFuncSetAttribute((const void*)k_bjacobi_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const size_t lds = lds_need(w) - 1024;
+    const void* kern = w == 16 ? (const void*)k_bjacobi_round_g<16>
+                     : w == 8 ? (const void*)k_bjacobi_round_g<8> : (const void*)k_bjacobi_round_g<4>;
+    BDG_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     for (int sweep = 0; sweep < 40; ++sweep) {
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, counter);
-        for (int rnd = 0; rnd < nblk - 1; ++rnd)
-            hipLaunchKernelGGL(k_bjacobi_round, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V, ldv, w,
-                               nblk, rnd, (const double*)frob2, counter);
+        for (int rnd = 0; rnd < nblk - 1; ++rnd) {
+            if (w == 16)
+                hipLaunchKernelGGL(k_bjacobi_round_g<16>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
+                                   ldv, nblk, rnd, (const double*)frob2, counter);
+            else if (w == 8)
+                hipLaunchKernelGGL(k_bjacobi_round_g<8>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
+                                   ldv, nblk, rnd, (const double*)frob2, counter);
+            else
+                hipLaunchKernelGGL(k_bjacobi_round_g<4>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
+                                   ldv, nblk, rnd, (const double*)frob2, counter);
+        }
         BDG_HIP(c, hipGetLastError());
         int h = 0;
         BDG_HIP(c, hipMemcpyAsync(&h, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
