@@ -130,14 +130,23 @@ __global__ void __launch_bounds__(1024) k_pchol_orth(int m, double2* A, int lda,
         __syncthreads();
         const int pj = perm[j];
         const double piv = sqrt(bestv);
-        // column j of L (stored by original row index): L[pi][j] = A[pi][pj] / piv
+        // column j of L (stored by original row index): L[pi][j] = A[pi][pj] / piv; A keeps
+        // its lower triangle in the original index order (row >= column), which the symmetric
+        // pivot swaps leave intact, so an entry above it is read as the mirror's conjugate
         for (int i = j + t; i < m; i += nt) {
             const int pi = perm[i];
-            const double2 a = A[(long long)pj * lda + pi];
+            double2 a;
+            if (pi >= pj) {
+                a = A[(long long)pj * lda + pi];
+            } else {
+                const double2 u = A[(long long)pi * lda + pj];
+                a = mk(u.x, -u.y);
+            }
             Lb[(long long)j * m + pi] = (i == j) ? mk(piv, 0.0) : mk(a.x / piv, a.y / piv);
         }
         __syncthreads();
-        // Schur complement update on the remaining rows/columns (four updates in flight)
+        // Schur complement update on the remaining rows/columns, lower triangle (original
+        // index order) only; four updates in flight
         const long long rem = m - j - 1;
         for (long long e0 = t; e0 < rem * rem; e0 += 4 * nt) {
             double2 av[4], pv[4];
@@ -146,8 +155,9 @@ __global__ void __launch_bounds__(1024) k_pchol_orth(int m, double2* A, int lda,
             for (int u = 0; u < 4; ++u) {
                 const long long e = e0 + (long long)u * nt;
                 ix[u] = -1;
-                if (e < rem * rem) {
-                    const int pi = perm[j + 1 + (int)(e % rem)], pl = perm[j + 1 + (int)(e / rem)];
+                const int pi = e < rem * rem ? perm[j + 1 + (int)(e % rem)] : 0;
+                const int pl = e < rem * rem ? perm[j + 1 + (int)(e / rem)] : 1;
+                if (e < rem * rem && pi >= pl) {
                     ix[u] = (long long)pl * lda + pi;
                     pv[u] = cmc(Lb[(long long)j * m + pi], Lb[(long long)j * m + pl]);
                     av[u] = A[ix[u]];
@@ -197,18 +207,21 @@ __global__ void __launch_bounds__(1024) k_plu_biorth(int p, int q, double2* B, i
     __syncthreads();
     const int mn = p < q ? p : q;
     int r = mn;
-    for (int j = 0; j < mn; ++j) {
-        const long long rp = p - j, rq = q - j;
+    {
+        // first pivot: the largest entry of B; later pivots come out of the Schur updates
         double v = -1.0;
         int idx = 0x7fffffff;
-        for (long long e = t; e < rp * rq; e += nt) {
-            const int i = j + (int)(e % rp), l = j + (int)(e / rp);
-            const double2 b = B[(long long)pc[l] * ldb + pr[i]];
+        for (long long e = t; e < (long long)p * q; e += nt) {
+            const int i = (int)(e % p), l = (int)(e / p);
+            const double2 b = B[(long long)l * ldb + i];
             const double a = b.x * b.x + b.y * b.y;
             const int code = i * 512 + l;
             if (a > v || (a == v && code < idx)) { v = a; idx = code; }
         }
         block_argmax(v, idx, sv, si, &bestv, &besti);
+    }
+    for (int j = 0; j < mn; ++j) {
+        const long long rp = p - j, rq = q - j;
         if (!(bestv > tol * tol)) { r = j; break; }
         if (t == 0) {
             const int i = besti / 512, l = besti % 512;
@@ -222,10 +235,14 @@ __global__ void __launch_bounds__(1024) k_plu_biorth(int p, int q, double2* B, i
             b = cdiv(b, piv);
         }
         __syncthreads();
+        // Schur update of the trailing block; the largest updated entry is the next pivot
         const long long nu = (rp - 1) * (rq - 1);
+        double v = -1.0;
+        int idx = 0x7fffffff;
         for (long long e0 = t; e0 < nu; e0 += 4 * nt) {
             double2 bv[4], pv[4];
             long long ix[4];
+            int code[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const long long e = e0 + (long long)u * nt;
@@ -233,15 +250,22 @@ __global__ void __launch_bounds__(1024) k_plu_biorth(int p, int q, double2* B, i
                 if (e < nu) {
                     const int i = j + 1 + (int)(e % (rp - 1)), l = j + 1 + (int)(e / (rp - 1));
                     ix[u] = (long long)pc[l] * ldb + pr[i];
+                    code[u] = i * 512 + l;
                     pv[u] = cm(B[(long long)pc[j] * ldb + pr[i]], B[(long long)pc[l] * ldb + pr[j]]);
                     bv[u] = B[ix[u]];
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (ix[u] >= 0) B[ix[u]] = mk(bv[u].x - pv[u].x, bv[u].y - pv[u].y);
+                if (ix[u] >= 0) {
+                    const double2 nb = mk(bv[u].x - pv[u].x, bv[u].y - pv[u].y);
+                    B[ix[u]] = nb;
+                    const double a = nb.x * nb.x + nb.y * nb.y;
+                    if (a > v || (a == v && code[u] < idx)) { v = a; idx = code[u]; }
+                }
         }
-        __syncthreads();
+        // (block_argmax synchronizes the workgroup before and after)
+        block_argmax(v, idx, sv, si, &bestv, &besti);
     }
     // T = L11^-1 (unit lower); Cg[pr[i]][c] = conj(T[c][i])
     auto Lacc = [&](int i, int k) -> double2 { return B[(long long)pc[k] * ldb + pr[i]]; };
