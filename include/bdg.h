@@ -123,9 +123,11 @@ bdg_status bdg_biortho(bdg_ctx* ctx, int nvec, void* F_dev, void* G_dev, double*
  * X0_dev: block x 6 npts complex128 start block in (f, g) form (NULL = complex normal
  * block drawn from `seed`).  omega (host, k): ascending; UV_dev (device, k x 6 npts
  * complex128): eigenvectors in (u, v) form with int |u|^2 - |v|^2 = 1 (i.e. <f, g> = 1/4);
- * may be NULL.  residual (host, k), iters (host) may be NULL.  Needs k <= block <= 6 npts
- * and block <= 160.  BDG_ENOCONV after max_iter iterations (outputs hold the last
- * iterate). */
+ * may be NULL.  residual (host, k), iters (host) may be NULL.  Needs
+ * 1 <= k <= block <= min(160, 3 npts - 4) (each half of a trial vector lives in 3 npts
+ * dimensions, less up to 4 deflated directions); BDG_EINVAL otherwise.  BDG_ENOCONV after
+ * max_iter iterations (outputs hold the last iterate); BDG_EBREAKDOWN when the projected
+ * problem keeps losing rank or definiteness after the basis refreshes. */
 bdg_status bdg_eigs(bdg_ctx* ctx, int k, int block, double tol, int max_iter,
                     const void* X0_dev, unsigned long long seed, double* omega, void* UV_dev,
                     double* residual, int* iters);

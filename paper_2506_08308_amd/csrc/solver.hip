@@ -474,7 +474,10 @@ bdg_status pcg_hplus(bdg_ctx* c, Small& w, long long nh, const double2* Np, int 
         hipLaunchKernelGGL(k_axpy, g1, dim3(256), 0, c->stream, nh, cmk<double2>(-alpha, 0.0), (const double2*)Ap, r);
         const double rn = std::sqrt(std::max(0.0, host_dot_re(c, w, nh, r, r, &st)));
         BDG_TRY(st);
-        if (rn <= tol * bnorm) return BDG_OK;
+        if (rn <= tol * bnorm) {
+            if (debug_on()) fprintf(stderr, "[bdg pcg] converged in %d iterations (%.2e)\n", it + 1, rn / bnorm);
+            return BDG_OK;
+        }
         BDG_TRY(launch_precond<double>(c, 3, 3, nh, r, z));
         BDG_TRY(project_out(c, w, nh, Np, np, z, 1));
         const double rz_new = host_dot_re(c, w, nh, z, r, &st);
@@ -1022,8 +1025,9 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
 extern "C" bdg_status bdg_eigs(bdg_ctx* c, int k, int block, double tol, int max_iter, const void* X0_dev,
                                unsigned long long seed, double* omega, void* UV_dev, double* residual, int* iters) {
     if (!c) return BDG_EINVAL;
-    if (k < 1 || block < k || block > 160 || (long long)block > 6 * c->npts)
-        return ctx_fail(c, BDG_EINVAL, "bdg_eigs: need 1 <= k <= block <= min(160, 6 npts)");
+    // each half (f or g) lives in 3 npts dimensions minus at most 4 deflated directions
+    if (k < 1 || block < k || block > 160 || (long long)block > 3 * c->npts - 4)
+        return ctx_fail(c, BDG_EINVAL, "bdg_eigs: need 1 <= k <= block <= min(160, 3 npts - 4)");
     if (!(tol > 0) || max_iter < 1) return ctx_fail(c, BDG_EINVAL, "bdg_eigs: bad tol or max_iter");
     if (!omega) return ctx_fail(c, BDG_EINVAL, "bdg_eigs: omega is null");
     if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "bdg_eigs: no ground state set");
@@ -1204,7 +1208,6 @@ extern "C" bdg_status bdg_eigs_grad(bdg_ctx* c, int k, const double* omega, cons
     const long long npts = c->npts, nh = 3 * npts;
     const bdg_problem& pr = c->prob;
     Small w;
-    BDG_TRY(small_alloc(c, w, 8));
     double2* Q = nullptr;      // orthonormal basis of span{Phi, S_z Phi} (complex, 2 columns)
     double* szphi = nullptr;
     double* dens = nullptr;
@@ -1214,6 +1217,14 @@ extern "C" bdg_status bdg_eigs_grad(bdg_ctx* c, int k, const double* omega, cons
     double2* ws = nullptr;
     double* part = nullptr;
     double* sums = nullptr;
+    // every exit path releases the workspace
+    auto release = defer([&] {
+        small_free(c, w);
+        for (void* p : {(void*)Q, (void*)szphi, (void*)dens, (void*)qv, (void*)y, (void*)yc, (void*)ws, (void*)part,
+                        (void*)sums})
+            ctx_free(c, p);
+    });
+    BDG_TRY(small_alloc(c, w, 8));
     const int nblk = (int)std::min<long long>(1024, (npts + RB2 - 1) / RB2);
     BDG_TRY(ctx_alloc(c, (void**)&Q, 2 * nh * sizeof(double2)));
     BDG_TRY(ctx_alloc(c, (void**)&szphi, nh * sizeof(double)));
@@ -1305,9 +1316,5 @@ extern "C" bdg_status bdg_eigs_grad(bdg_ctx* c, int k, const double* omega, cons
         j0 = j1;
     }
     BDG_HIP(c, hipStreamSynchronize(c->stream));
-    small_free(c, w);
-    for (void* p : {(void*)Q, (void*)szphi, (void*)dens, (void*)qv, (void*)y, (void*)yc, (void*)ws, (void*)part,
-                    (void*)sums})
-        ctx_free(c, p);
     return BDG_OK;
 }
