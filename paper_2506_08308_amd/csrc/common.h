@@ -113,6 +113,10 @@ template <typename R>
 bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
                           const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y);
 
+// Mixed form of launch_precond on nvec (f, g) pairs: float32 passes in place on X32 (lo: the
+// f halves, hi: the g halves, vector stride vstride), the last pass writes float64 into Y64.
+bdg_status launch_precond_mixed(bdg_ctx* c, int nvec, BlockRef<float2> X32, BlockRef<double2> Y64);
+
 // Y = D F^-1 m(k) F D X with m = |k|^2/2 (precond = 0) or (|k|^2/2 + shift)^-1
 // (precond = 1); D = wgt (npts real, pointwise) or 1 when wgt is null.
 template <typename R>

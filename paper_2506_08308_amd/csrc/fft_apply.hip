@@ -110,12 +110,13 @@ __device__ __forceinline__ R multiplier(const MultSpec& m, int mx, int my, int m
 // ----------------------------------------------------------------------------------------
 // wgt (optional, npts real): pointwise factor applied before a forward transform and after
 // an inverse one (the D of a symmetric preconditioner D T D).
-template <typename V, int N, bool INV, int MODE>
-__global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<V> out,
+template <typename V, int N, bool INV, int MODE, typename VO = V>
+__global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<VO> out,
                                                long long nfields, long long lines_per_field,
                                                const V* __restrict__ tw, MultSpec ms, int ny,
                                                const decltype(V::x)* __restrict__ wgt) {
     using R = decltype(V::x);
+    using RO = decltype(VO::x);
     constexpr int Q = N / 4;
     constexpr int LPW = (1024 / N) > 0 ? (1024 / N) : 1;
     __shared__ V lds[LPW * N];
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<
     const long long f = valid ? gl / lines_per_field : 0;
     const long long l = valid ? gl % lines_per_field : 0;
     const V* src = in.field(f) + l * N;
-    V* dst = out.field(f) + l * N;
+    VO* dst = out.field(f) + l * N;
     V v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<
     }
     if (valid) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[i + r * Q] = v[r];
+        for (int r = 0; r < 4; ++r) dst[i + r * Q] = cmk<VO>((RO)v[r].x, (RO)v[r].y);
     }
 }
 
@@ -367,8 +368,8 @@ MultSpec make_ms(bdg_ctx* c, int precond, double shift) {
         default: return ctx_fail(c, BDG_EINVAL, "unsupported axis length"); \
     }
 
-template <typename V, bool INV, int MODE>
-bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<V> out, long long nfields, MultSpec ms,
+template <typename V, bool INV, int MODE, typename VO = V>
+bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<VO> out, long long nfields, MultSpec ms,
                      const decltype(V::x)* wgt = nullptr) {
     const int N = c->n[0];
     const long long lpf = c->npts / N;
@@ -376,7 +377,7 @@ bdg_status run_xpass(bdg_ctx* c, FieldAddr<const V> in, FieldAddr<V> out, long l
         constexpr int LPW = (1024 / NN) > 0 ? (1024 / NN) : 1;
         const long long nl = nfields * lpf;
         dim3 grid((unsigned)((nl + LPW - 1) / LPW));
-        hipLaunchKernelGGL((k_xpass<V, NN, INV, MODE>), grid, dim3(LPW * (NN / 4)), 0, c->stream,
+        hipLaunchKernelGGL((k_xpass<V, NN, INV, MODE, VO>), grid, dim3(LPW * (NN / 4)), 0, c->stream,
                            in, out, nfields, lpf, (const V*)tw_of<decltype(V::x)>(c, 0), ms, c->n[1], wgt);
     });
     return hip_check(c, hipGetLastError(), "k_xpass");
@@ -496,6 +497,27 @@ bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
                           const typename cplx_of<R>::type* X, typename cplx_of<R>::type* Y) {
     if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "preconditioner needs the ground state");
     return launch_fourier<R>(c, nfields, fpv, vstride, X, Y, 1, c->pshift, pw_of<R>(c));
+}
+
+bdg_status launch_precond_mixed(bdg_ctx* c, int nvec, BlockRef<float2> X32, BlockRef<double2> Y64) {
+    if (nvec <= 0) return BDG_OK;
+    if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "preconditioner needs the ground state");
+    MultSpec ms = make_ms(c, 1, c->pshift);
+    const long long nf = 6LL * nvec;
+    FieldAddr<float2> xa = fa_block<float2>(X32.lo, X32.hi, X32.vstride, c->npts);
+    FieldAddr<const float2> xc = fa_block<const float2>(X32.lo, X32.hi, X32.vstride, c->npts);
+    FieldAddr<double2> ya = fa_block<double2>(Y64.lo, Y64.hi, Y64.vstride, c->npts);
+    const float* wgt = c->pw32;
+    if (c->dim == 1) return run_xpass<float2, false, 1, double2>(c, xc, ya, nf, ms, wgt);
+    BDG_TRY((run_xpass<float2, false, 0>(c, xc, xa, nf, ms, wgt)));
+    if (c->dim == 2) {
+        BDG_TRY((run_strided<float2, false, 1>(c, xa, nf, 1, ms)));
+    } else {
+        BDG_TRY((run_strided<float2, false, 0>(c, xa, nf, 1, ms)));
+        BDG_TRY((run_strided<float2, false, 1>(c, xa, nf, 2, ms)));
+        BDG_TRY((run_strided<float2, true, 0>(c, xa, nf, 1, ms)));
+    }
+    return run_xpass<float2, true, 0, double2>(c, xc, ya, nf, ms, wgt);
 }
 
 template bdg_status launch_fourier<double>(bdg_ctx*, int, int, long long, const double2*, double2*, int, double,

@@ -90,6 +90,19 @@ __global__ void k_small_scale_rows(int m, double2* A, int lda, const double* __r
     A[(long long)j * lda + i] = cmk<double2>(a.x * s[i], a.y * s[i]);
 }
 
+// the same in float32 output (the mixed form's correction block)
+__global__ void k_cols_axmy_idx32(long long K, const double2* __restrict__ X, const double2* __restrict__ Y,
+                                  long long ld, const double* __restrict__ w, const int* __restrict__ idx,
+                                  float2* __restrict__ Z, long long ldz) {
+    const int t = blockIdx.y;
+    const long long j = idx[t];
+    const double s = w[j];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        double2 a = X[j * ld + i], b = Y[j * ld + i];
+        Z[t * ldz + i] = cmk<float2>((float)(a.x - s * b.x), (float)(a.y - s * b.y));
+    }
+}
+
 // Y(:, t) = X(:, idx[t]) for t < gridDim.y; X and Y must not overlap
 __global__ void k_cols_gather(long long K, const double2* __restrict__ X, long long ldx, const int* __restrict__ idx,
                               double2* __restrict__ Y, long long ldy) {
@@ -839,24 +852,26 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             continue;
         }
         // residual directions of the active columns: f-direction H_+ f - w g, g-direction
-        // H_- g - w f, then the preconditioner (its precision only affects the rate)
+        // H_- g - w f, then the preconditioner (its precision only affects the rate; the
+        // mixed form writes the residuals in float32 and gets float64 back from the
+        // preconditioner's last pass)
         BDG_TRY(h2d(c, d_act, act.data(), nact * sizeof(int)));
-        hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HF,
-                           (const double2*)G, nh, (const double*)d_om, (const int*)d_act, Wf, nh);
-        hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HG,
-                           (const double2*)F, nh, (const double*)d_om, (const int*)d_act, Wg, nh);
-        BDG_HIP(c, hipGetLastError());
         if (mixed) {
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wf, nh,
-                               w32, nh);
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wg, nh,
+            hipLaunchKernelGGL(k_cols_axmy_idx32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HF,
+                               (const double2*)G, nh, (const double*)d_om, (const int*)d_act, w32, nh);
+            hipLaunchKernelGGL(k_cols_axmy_idx32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HG,
+                               (const double2*)F, nh, (const double*)d_om, (const int*)d_act,
                                w32 + (size_t)nact * nh, nh);
-            BDG_TRY(launch_precond<float>(c, 6 * nact, 3, nh, w32, w32));
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const float2*)w32, nh,
-                               Wf, nh);
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact,
-                               (const float2*)(w32 + (size_t)nact * nh), nh, Wg, nh);
+            BDG_HIP(c, hipGetLastError());
+            BlockRef<float2> x32{w32, w32 + (size_t)nact * nh, nh};
+            BlockRef<double2> y64{Wf, Wg, nh};
+            BDG_TRY(launch_precond_mixed(c, nact, x32, y64));
         } else {
+            hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HF,
+                               (const double2*)G, nh, (const double*)d_om, (const int*)d_act, Wf, nh);
+            hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HG,
+                               (const double2*)F, nh, (const double*)d_om, (const int*)d_act, Wg, nh);
+            BDG_HIP(c, hipGetLastError());
             BDG_TRY(launch_precond<double>(c, 3 * nact, 3, nh, Wf, Wf));
             BDG_TRY(launch_precond<double>(c, 3 * nact, 3, nh, Wg, Wg));
         }
