@@ -7,16 +7,24 @@
 // implementation is a locally optimal block iteration of the Bai-Li family:
 //   basis      S_f = [F, W_f, P_f], S_g = [G, W_g, P_g] and their images H_+ S_f, H_- S_g;
 //   residual   R = H_+ F - G diag(w) (f-direction), H_- G - F diag(w) (g-direction);
-//   correction W = (|k|^2/2 + sigma)^-1 R, projected off the generalized nullspace
-//              (f orthogonal to ns(H_-), g orthogonal to ns(H_+) + Jordan partners);
-//   projection each basis is made orthonormal on its own (rank-revealing), the pairing
-//              matrix of the two orthonormal bases is bi-orthogonalized by an SVD
-//              (B = U Sigma V^H, C_f = R_f V Sigma^-1/2, C_g = R_g U Sigma^-1/2), and the
+//   correction W = D (|k|^2/2 + sigma)^-1 D R (kinetic-potential preconditioner, D^2 =
+//              sigma / (sigma + max(V - mu_0, 0)), sigma = max(mu_0 / 2, 1/2)) for the active
+//              columns only (res > tol; converged columns are soft-locked), projected off
+//              the generalized nullspace (f orthogonal to ns(H_-), g orthogonal to
+//              ns(H_+) + Jordan partners);
+//   projection each basis is made orthonormal on its own by a pivoted Cholesky of its
+//              diagonally scaled Gram matrix (rank-revealing: S R_f, S R_g), the pairing
+//              matrix B = R_g^H S_g^H S_f R_f of the two orthonormal bases is
+//              bi-orthogonalized by an LU with complete pivoting (the modified Gram-Schmidt
+//              bi-orthogonalization in factored form: C_f = R_f P_c^T [U11^-1; 0],
+//              C_g = R_g P_r^T [L11^-H; 0], C_g^H B_r C_f = I), and the
 //              projected problem K b = w a, M a = w b (M = C_f^H S_f^H H_+ S_f C_f,
 //              K = C_g^H S_g^H H_- S_g C_g) is solved through the Cholesky factors
 //              M = L_M L_M^H, K = L_K L_K^H and the SVD L_K^H L_M = U_G diag(w) V_G^H:
 //              a = L_K u, b = L_M v;
-//   update     F <- S_f a, G <- S_g b (and images), P from the W and P rows.
+//   update     P <- [W, P] a_{W,P} (and images), then F <- F a_F + P, G likewise with b;
+//              W and P keep their raw scale, their unit-column scaling enters the Gram
+//              matrices and the coefficient rows.
 // Gram matrices and updates run on the FP64 matrix cores; the projected problems on the
 // device in FP64; the host only reads back residual norms and small singular values.
 #include "common.h"
