@@ -200,35 +200,37 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
 // Z may be Y (each element is read before it is written by the same lane); Y must not
 // overlap S unless one workgroup covers all nb columns (grid.y == 1).
 // ----------------------------------------------------------------------------------------
-template <int CB>
+template <int CB, int RA>
 __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long long lds, int m,
                                                 const double2* __restrict__ Cm, int ldcm, int nb, double beta,
                                                 const double2* Z, long long ldz, double2* Y, long long ldy) {
-    // LDS chunks of UL columns of S (128 rows) and UL rows of Cm (16 CB columns); the next
-    // chunk is held in registers while the MFMAs of the current one run
+    // a workgroup owns RW = 64 RA rows (each wave 16 RA rows) and 16 CB columns; LDS chunks of
+    // UL columns of S and UL rows of Cm, the next chunk held in registers while the MFMAs of
+    // the current one run
     constexpr int UL = 16;
     constexpr int NC = 16 * CB;
-    constexpr int SP = 129;                          // row pitch of the S chunk (double2)
+    constexpr int RW = 64 * RA;
+    constexpr int SP = RW + 1;                       // row pitch of the S chunk (double2)
     __shared__ double2 lsS[UL * SP];
     __shared__ double2 lsC[UL * NC];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const long long R0 = (long long)blockIdx.x * 128;
+    const long long R0 = (long long)blockIdx.x * RW;
     const int j0 = blockIdx.y * NC;
     const int ri = lane & 15, kq = lane >> 4;
-    const int wr = wave * 32;
-    d4 accr[2][CB], acci[2][CB];
+    const int wr = wave * 16 * RA;
+    d4 accr[RA][CB], acci[RA][CB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < CB; ++b) { accr[a][b] = d4{0, 0, 0, 0}; acci[a][b] = d4{0, 0, 0, 0}; }
-    constexpr int SPASS = UL * 128 / 256;             // 8 S elements per thread
-    constexpr int CPASS = (UL * NC + 255) / 256;      // <= 5 Cm elements per thread
+    constexpr int SPASS = UL * RW / 256;
+    constexpr int CPASS = (UL * NC + 255) / 256;
     double2 rs[SPASS], rc[CPASS];
     auto gload = [&](int l0) {
 #pragma unroll
         for (int u = 0; u < SPASS; ++u) {
             const int idx = u * 256 + t;
-            const int l = l0 + idx / 128, row = idx % 128;
+            const int l = l0 + idx / RW, row = idx % RW;
             rs[u] = double2{0, 0};
             if (l < m && R0 + row < K) rs[u] = seg_col(segs, l, lds)[R0 + row];
         }
@@ -246,7 +248,7 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
 #pragma unroll
         for (int u = 0; u < SPASS; ++u) {
             const int idx = u * 256 + t;
-            lsS[(idx / 128) * SP + idx % 128] = rs[u];
+            lsS[(idx / RW) * SP + idx % RW] = rs[u];
         }
 #pragma unroll
         for (int u = 0; u < CPASS; ++u) {
@@ -258,14 +260,14 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
 #pragma unroll
         for (int ks = 0; ks < UL; ks += 4) {
             const int l = ks + kq;
-            double2 sv[2];
+            double2 sv[RA];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) sv[a] = lsS[l * SP + wr + 16 * a + ri];
+            for (int a = 0; a < RA; ++a) sv[a] = lsS[l * SP + wr + 16 * a + ri];
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
                 const double2 cv = lsC[l * NC + 16 * b + ri];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
+                for (int a = 0; a < RA; ++a) {
                     accr[a][b] = mfma(sv[a].x, cv.x, accr[a][b]);
                     accr[a][b] = mfma(-sv[a].y, cv.y, accr[a][b]);
                     acci[a][b] = mfma(sv[a].x, cv.y, acci[a][b]);
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
         }
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int j = j0 + 16 * b + (lane & 15);
@@ -723,14 +725,20 @@ bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long l
     if (!make_seglist(segs, nseg, &sl, &m)) return ctx_fail(c, BDG_EINVAL, "update: 1..4 segments");
     const int cb = std::min(5, (nb + 15) / 16);
     const int ctiles = (nb + 16 * cb - 1) / (16 * cb);
-    dim3 grid((unsigned)((K + 127) / 128), (unsigned)ctiles);
+    // 16 rows per wave (RA = 1): 10 accumulator tiles per wave leave room for two waves per
+    // SIMD, measured 25 % faster on the 3-D solve than 32 rows per wave
+    constexpr int RA = 1;
+    dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), (unsigned)ctiles);
+#define BDG_UPD(CBV) \
+    hipLaunchKernelGGL((k_update<CBV, RA>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy)
     switch (cb) {
-        case 1: hipLaunchKernelGGL(k_update<1>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
-        case 2: hipLaunchKernelGGL(k_update<2>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
-        case 3: hipLaunchKernelGGL(k_update<3>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
-        case 4: hipLaunchKernelGGL(k_update<4>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
-        default: hipLaunchKernelGGL(k_update<5>, grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy); break;
+        case 1: BDG_UPD(1); break;
+        case 2: BDG_UPD(2); break;
+        case 3: BDG_UPD(3); break;
+        case 4: BDG_UPD(4); break;
+        default: BDG_UPD(5); break;
     }
+#undef BDG_UPD
     return hip_check(c, hipGetLastError(), "k_update");
 }
 
