@@ -114,3 +114,21 @@ def test_mass_and_magnetization_edges():
     say(f"   max rel err {rel.max():.2e}")
     assert rel.max() <= 1e-9
     ctx.close()
+
+
+def test_solves_are_bitwise_deterministic():
+    """Fixed-order reductions everywhere: two solves from the same seed (device start block)
+    and two applies give bit-identical results."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Form
+    w = W.Workload("2d_32_fm", 2, (32, 32), (6.0, 6.0), "harmonic2", 20.0, -1.0, 0.1)
+    say("determinism", w.name)
+    ctx = make_ctx(w)
+    ctx.ground_state(tol=1e-12)
+    a = ctx.eigs(8, 12, tol=1e-10, seed=11)
+    b = ctx.eigs(8, 12, tol=1e-10, seed=11)
+    assert a["omega"] == b["omega"] and a["iters"] == b["iters"]
+    assert torch.equal(a["uv"], b["uv"])
+    X = torch.from_numpy(W.random_block((3, 6) + w.shape, seed=2)).to("cuda")
+    assert torch.equal(ctx.apply(X, Form.FG), ctx.apply(X, Form.FG))
+    ctx.close()
