@@ -226,6 +226,127 @@ def kernels_only(w):
     ctx.close()
 
 
+# ------------------------------------------------------------------------------------------
+# The paper's own campaigns (Section 4.1): accuracy of the Kohn modes against the analytical
+# eigenpairs of the harmonic trap (Theorem "Analytical eigenpairs") and time against DOF.
+# Ferromagnetic (beta_n, beta_s) = (885.4, -4.1), anti-ferromagnetic (240.8, 7.5), M = 0
+# (the paper does not state M), box [-16, 16]^d in 1-D/2-D and [-8, 8]^3 in 3-D.
+# ------------------------------------------------------------------------------------------
+CAMPAIGN_BETAS = {"FM": (885.4, -4.1), "AFM": (240.8, 7.5)}
+ACCURACY_CASES = [("I", "harmonic1", 1, 16.0, (32, 64, 128, 256, 512)),
+                  ("II", "harmonic2", 2, 16.0, (32, 64, 128, 256, 512)),
+                  ("III", "harmonic2_aniso", 2, 16.0, (32, 64, 128, 256, 512)),
+                  ("IV", "harmonic3", 3, 8.0, (16, 32, 64, 128))]
+
+
+def _kohn_errors(w, phi, omega, uv, gammas):
+    """e_omega and e_uv of the paper for each trap frequency gamma_a: the computed modes nearest
+    gamma_a (as many as gamma_a occurs) against the analytical eigenspace spanned by
+    (gamma^-1/2 d_a Phi -+ gamma^1/2 x_a Phi) / sqrt 2 for all axes with that frequency."""
+    coords = W.coordinates(w)                      # per axis, grid shaped, x first
+    phi = np.asarray(phi)
+    out = []
+    om = np.asarray(omega)
+    used = set()
+    for a, g in enumerate(gammas):
+        same = [b for b, gb in enumerate(gammas) if gb == g]
+        U, Vv = [], []
+        for b in same:
+            ax = phi.ndim - 1 - b                  # array axis of coordinate b (x is last)
+            n = phi.shape[ax]
+            kk = np.fft.fftfreq(n, d=1.0 / n) * np.pi / w.L[b]
+            kk[n // 2] = 0.0                       # first derivative: Nyquist mode dropped
+            shape = [1] * phi.ndim
+            shape[ax] = n
+            dphi = np.real(np.fft.ifft(1j * kk.reshape(shape) * np.fft.fft(phi, axis=ax), axis=ax))
+            xphi = coords[b][None] * phi
+            U.append(((g ** -0.5) * dphi - (g ** 0.5) * xphi).ravel() / np.sqrt(2))
+            Vv.append(((g ** -0.5) * dphi + (g ** 0.5) * xphi).ravel() / np.sqrt(2))
+        QU, _ = np.linalg.qr(np.array(U).T)
+        QV, _ = np.linalg.qr(np.array(Vv).T)
+        order = [j for j in np.argsort(np.abs(om - g)) if j not in used]
+        j = int(order[0])
+        used.add(j)
+        u = uv[j, :3].ravel()
+        v = uv[j, 3:].ravel()
+        eu = np.linalg.norm(u - QU @ (QU.conj().T @ u)) / np.linalg.norm(u)
+        ev = np.linalg.norm(v - QV @ (QV.conj().T @ v)) / np.linalg.norm(v)
+        out.append({"axis": "xyz"[a], "gamma": g, "omega": float(om[j]), "e_omega": abs(om[j] - g) / g,
+                    "e_uv": float(eu + ev)})
+    return out
+
+
+def _ground_state(ctx, tol=1e-12, max_iter=400000, chunk=20000):
+    """bdg_ground_state in chunks of `chunk` steps, each continuing from the last iterate, with
+    a progress line per chunk (a slow flow stays visibly alive)."""
+    phi, its = None, 0
+    while True:
+        phi, mu, res, n = ctx.ground_state(phi0=phi, tol=tol, max_iter=chunk, check=False)
+        its += n
+        if res <= tol or its >= max_iter:
+            return phi, mu, res, its
+        log(f"  ground state: {its} steps, residual {res:.2e}")
+
+
+def campaign_accuracy(k=40, block=48, dims=(1, 2, 3)):
+    import torch
+    for case, pot, d, L, ns in ACCURACY_CASES:
+        if d not in dims:
+            continue
+        for kind, (bn, bs) in CAMPAIGN_BETAS.items():
+            for n in ns:
+                w = W.Workload(f"acc_{case}_{kind}_{n}", d, (n,) * d, (L,) * d, pot, bn, bs, 0.0, k=k,
+                               block=block)
+                log(f"accuracy {w.name}")
+                ctx = _context(w)
+                t0 = time.time()
+                phi, mu, gres, gits = _ground_state(ctx)
+                # the k lowest modes must reach the largest trap frequency (the Kohn modes sit at
+                # omega = gamma_a); widen the solve while they do not
+                kk, bb = k, block
+                while True:
+                    out = ctx.eigs(kk, bb, tol=1e-10, max_iter=1500, seed=0, check=False)
+                    if max(out["omega"]) > 1.05 * max(W.TRAP_GAMMAS[pot]) or kk >= 148:
+                        break
+                    bb = min(min(2 * kk, 148) + 12, 3 * w.npts - 4)
+                    kk = min(2 * kk, 148, bb)
+                torch.cuda.synchronize()
+                errs = _kohn_errors(w, phi.cpu().numpy(), out["omega"], out["uv"].cpu().numpy(),
+                                    W.TRAP_GAMMAS[pot])
+                ctx.close()
+                print(json.dumps({"campaign": "accuracy", "case": case, "kind": kind, "dim": d, "N": n,
+                                  "h": 2 * L / n, "ground_state_iters": gits, "ground_state_residual": gres,
+                                  "k": kk, "eig_status": out["status"], "eig_iters": out["iters"],
+                                  "max_residual": max(out["residual"]),
+                                  "seconds": round(time.time() - t0, 2), "kohn": errs}), flush=True)
+
+
+def campaign_efficiency(k=40, block=48, tol=1e-8, dims=(2, 3)):
+    import torch
+    for d, L, ns in ((2, 16.0, (32, 64, 128, 256, 512, 1024)), (3, 8.0, (16, 32, 64, 128))):
+        if d not in dims:
+            continue
+        for kind, (bn, bs) in CAMPAIGN_BETAS.items():
+            for n in ns:
+                w = W.Workload(f"eff_{d}d_{kind}_{n}", d, (n,) * d, (L,) * d, f"harmonic{d}", bn, bs, 0.0, k=k,
+                               block=block)
+                log(f"efficiency {w.name}")
+                ctx = _context(w)
+                _ground_state(ctx)
+                torch.cuda.synchronize()
+                t0 = time.time()
+                out = ctx.eigs(k, block, tol=tol, max_iter=3000, seed=0, want_vectors=False)
+                torch.cuda.synchronize()
+                dt = time.time() - t0
+                st = ctx.stats()
+                ctx.close()
+                print(json.dumps({"campaign": "efficiency", "dim": d, "kind": kind, "N": n, "DOF": 6 * n ** d,
+                                  "nev": k, "block": block, "tol": tol, "seconds": round(dt, 3),
+                                  "iters": out["iters"], "phase_ms": {kk: round(st[kk], 1) for kk in (
+                                      "apply_ms", "precond_ms", "gram_ms", "small_ms", "update_ms", "setup_ms")}}),
+                      flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +357,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 solve timed beside the mixed one")
     ap.add_argument("--kernels-only", action="store_true")
+    ap.add_argument("--campaign", choices=("accuracy", "efficiency"),
+                    help="the paper's accuracy (Kohn modes vs h) or efficiency (time vs DOF) campaign")
+    ap.add_argument("--campaign-dims", default="1,2,3", help="comma-separated dimensions to run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU; the multi-GPU sharding is designed, not built. "
@@ -248,6 +372,13 @@ def main():
         w64 = None
     if args.kernels_only:
         kernels_only(w)
+        return
+    dims = tuple(int(x) for x in args.campaign_dims.split(","))
+    if args.campaign == "accuracy":
+        campaign_accuracy(dims=dims)
+        return
+    if args.campaign == "efficiency":
+        campaign_efficiency(dims=dims)
         return
     X0 = torch.from_numpy(W.start_block(w)).to("cuda")
     ctx, out, times, gs_s = solve(w, X0, args.steps, args.warmup, args.max_iter)

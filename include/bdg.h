@@ -57,7 +57,7 @@ typedef enum { BDG_FORM_UV = 0, BDG_FORM_FG = 1 } bdg_form;
 
 typedef struct {
     int dim;              /* 1, 2 or 3 */
-    int n[3];             /* points per axis (x, y, z); powers of two, 8 <= n <= 512; unused axes ignored */
+    int n[3];             /* points per axis (x, y, z); powers of two, 8 <= n <= 1024; unused axes ignored */
     double L[3];          /* half box lengths (> 0) */
     double beta_n;        /* density interaction (eq. GPE) */
     double beta_s;        /* spin-exchange interaction: < 0 ferromagnetic, > 0 antiferromagnetic */
@@ -67,7 +67,7 @@ typedef struct {
 } bdg_problem;
 
 /* Create a context: validates the problem (BDG_EINVAL on dim outside 1..3, n not a power of
- * two in [8, 512], L <= 0, mass <= 0, M outside (-1, 1), non-finite beta or V), copies V
+ * two in [8, 1024], L <= 0, mass <= 0, M outside (-1, 1), non-finite beta or V), copies V
  * (npts float64, device) and builds twiddle and wavenumber tables.  Ownership of the
  * context passes to the caller; release it with bdg_destroy. */
 bdg_status bdg_create(const bdg_problem* problem, const double* V_dev, void* hip_stream,

@@ -144,7 +144,7 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     if (!pr || !V_dev) return BDG_EINVAL;
     if (pr->dim < 1 || pr->dim > 3) return BDG_EINVAL;
     for (int a = 0; a < pr->dim; ++a) {
-        if (!is_pow2(pr->n[a]) || pr->n[a] < 8 || pr->n[a] > 512) return BDG_EINVAL;
+        if (!is_pow2(pr->n[a]) || pr->n[a] < 8 || pr->n[a] > 1024) return BDG_EINVAL;
         if (!(pr->L[a] > 0) || !std::isfinite(pr->L[a])) return BDG_EINVAL;
     }
     if (!std::isfinite(pr->beta_n) || !std::isfinite(pr->beta_s)) return BDG_EINVAL;

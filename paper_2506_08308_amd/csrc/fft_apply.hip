@@ -221,7 +221,10 @@ __global__ void __launch_bounds__(512) k_strided(FieldAddr<V> io, long long nfie
 // ----------------------------------------------------------------------------------------
 template <int N> struct CoupleCfg {
     static constexpr int QL = (256 / N) > 0 ? (256 / N) : 1;
-    static constexpr int THREADS = 6 * QL * (N / 4);
+    // fields per thread: a 1024-point line needs 256 threads per field, so six fields take
+    // two rounds of 768 threads (the workgroup limit is 1024)
+    static constexpr int FH = (6 * QL * (N / 4) > 1024) ? 2 : 1;
+    static constexpr int THREADS = 6 * QL * (N / 4) / FH;
 };
 
 template <typename V, int N, int FORM, int TRANS, bool FULL>
@@ -232,9 +235,10 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
     using R = decltype(V::x);
     constexpr int Q = N / 4;
     constexpr int QL = CoupleCfg<N>::QL;
+    constexpr int FH = CoupleCfg<N>::FH;
     __shared__ V lds[6 * QL * N];
     const int t = threadIdx.x;
-    const int fld = t / (QL * Q);
+    const int fld0 = t / (QL * Q);            // fields fld0 + h * (6 / FH), h < FH
     const int q = (t / Q) % QL;
     const int i = t % Q;
     const long long b = blockIdx.x;
@@ -243,24 +247,32 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
     const long long l = l0 + q;
     const bool valid = l < lines_per_field;
     const long long npts = xin.npts;
-    V v[4];
-    if (FULL) {
-        const V* src = xin.field(vec * 6 + fld) + l * N;
+    V v[FH][4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
-        line_fft<V, N, false>(v, i, lds, (fld * QL + q) * N, 1, tw);
-        const int my = (int)(l % ny), mz = (int)(l / ny);
+    for (int h = 0; h < FH; ++h) {
+        const int fld = fld0 + h * (6 / FH);
+        if (FULL) {
+            const V* src = xin.field(vec * 6 + fld) + l * N;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], multiplier<R>(ms, i + r * Q, my, mz));
-    } else {
-        const V* src = yout.field(vec * 6 + fld) + l * N;
+            for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+            line_fft<V, N, false>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
+            const int my = (int)(l % ny), mz = (int)(l / ny);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+            for (int r = 0; r < 4; ++r) v[h][r] = cscale(v[h][r], multiplier<R>(ms, i + r * Q, my, mz));
+        } else {
+            const V* src = yout.field(vec * 6 + fld) + l * N;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+        }
+        line_fft<V, N, true>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
     }
-    line_fft<V, N, true>(v, i, lds, (fld * QL + q) * N, 1, tw);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) lds[(fld * QL + q) * N + i + r * Q] = v[r];
+    for (int h = 0; h < FH; ++h) {
+        const int fld = fld0 + h * (6 / FH);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lds[(fld * QL + q) * N + i + r * Q] = v[h][r];
+    }
     __syncthreads();
     // coupling: one grid point per thread iteration
     const V* x0 = xin.field(vec * 6 + 0);
@@ -365,6 +377,7 @@ MultSpec make_ms(bdg_ctx* c, int precond, double shift) {
         case 128: { constexpr int NN = 128; __VA_ARGS__; } break;        \
         case 256: { constexpr int NN = 256; __VA_ARGS__; } break;        \
         case 512: { constexpr int NN = 512; __VA_ARGS__; } break;        \
+        case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;      \
         default: return ctx_fail(c, BDG_EINVAL, "unsupported axis length"); \
     }
 

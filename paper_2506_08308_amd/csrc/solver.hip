@@ -30,6 +30,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -259,6 +260,27 @@ dim3 grid_cols(long long K, int ncols) {
 // ---------------------------------------------------------------------------------------
 // Host-side helpers
 // ---------------------------------------------------------------------------------------
+// max over grid points of the row sums |H_+(x)|, |H_-(x)| of the pointwise 3x3 blocks (12
+// fields: the symmetric 00, 01, 02, 11, 12, 22 entries of H_+ then of H_-); one partial per block
+__global__ void __launch_bounds__(256) k_coef_bound(long long npts, const double* __restrict__ coef,
+                                                    double* __restrict__ part) {
+    __shared__ double red[4];
+    double mx = 0;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double* S = coef + (long long)6 * h * npts + p;
+            const double a00 = fabs(S[0]), a01 = fabs(S[npts]), a02 = fabs(S[2 * npts]);
+            const double a11 = fabs(S[3 * npts]), a12 = fabs(S[4 * npts]), a22 = fabs(S[5 * npts]);
+            mx = fmax(mx, fmax(a00 + a01 + a02, fmax(a01 + a11 + a12, a02 + a12 + a22)));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 struct Small {
     int cap = 0;                 // max dimension
     double2* buf[14] = {};
@@ -555,12 +577,28 @@ bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double null_tol) 
     if (nc[3] > 1e-20 * cmax && std::sqrt(np_[3]) <= null_tol * std::sqrt(nc[3])) {
         BDG_TRY(orthonormalize(c, w, nh, cand + 3 * nh, 1, Np, 1e-10, &pp));
     }
-    // sources of the Jordan partners: part of N_- orthogonal to N_+
+    // sources of the Jordan partners: part of N_- orthogonal to N_+.  A column that keeps less
+    // than 1e-4 of its norm after the projection lies in N_+ up to the ground state's own
+    // error (at M = 0 in the ferromagnetic phase K Phi = -S_z Phi): it has no partner, and
+    // rescaling its remainder would deflate that error pattern, a smooth low-mode direction
     double2* src = img + nh;       // up to 3 columns
     BDG_HIP(c, hipMemcpyAsync(keep, d.Nm, d.pm * nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    double n0[3] = {0, 0, 0}, n1[3] = {0, 0, 0};
+    BDG_TRY(colnorm2(c, nh, d.pm, keep, nh, w.s[0]));
+    BDG_TRY(d2h(c, n0, w.s[0], d.pm * sizeof(double)));
     BDG_TRY(project_out(c, w, nh, Np, pp, keep, d.pm));
+    BDG_TRY(colnorm2(c, nh, d.pm, keep, nh, w.s[0]));
+    BDG_TRY(d2h(c, n1, w.s[0], d.pm * sizeof(double)));
+    int nsrc = 0;
+    for (int j = 0; j < d.pm; ++j) {
+        if (!(n1[j] >= 1e-8 * n0[j])) continue;
+        if (nsrc != j)
+            BDG_HIP(c, hipMemcpyAsync(keep + nsrc * nh, keep + j * nh, nh * sizeof(double2), hipMemcpyDeviceToDevice,
+                                      c->stream));
+        ++nsrc;
+    }
     int ps = 0;
-    BDG_TRY(orthonormalize(c, w, nh, keep, d.pm, src, 1e-8, &ps));
+    BDG_TRY(orthonormalize(c, w, nh, keep, nsrc, src, 1e-8, &ps));
     // partners into the columns after N_+
     double2* qcols = cand;         // [N_+, partners], up to 4 columns
     if (pp) BDG_HIP(c, hipMemcpyAsync(qcols, Np, nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
@@ -648,7 +686,32 @@ struct EigsOpts {
     double rise_factor = 4.0;
     double rtol32 = 1e-10;      // cut-offs while images carry float32 rounding
     double eps32 = 1e-8;
+    double floor_c = 100.0;     // a column also counts as converged once its residual reaches
+                                // floor_c * eps ||H|| / |omega|, the float64 rounding floor of
+                                // the relative residual (a smaller tol is not attainable there)
 };
+
+// upper bound of ||H||: largest kinetic symbol plus the largest pointwise row sum of H_+-
+bdg_status operator_bound(bdg_ctx* c, double* out) {
+    double kin = 0;
+    for (int a = 0; a < c->dim; ++a) {
+        const double kmax = M_PI * c->n[a] / (2.0 * c->L[a]);
+        kin += 0.5 * kmax * kmax;
+    }
+    constexpr int NB = 256;
+    double* part = nullptr;
+    BDG_TRY(ctx_alloc(c, (void**)&part, NB * sizeof(double)));
+    hipLaunchKernelGGL(k_coef_bound, dim3(NB), dim3(256), 0, c->stream, c->npts, (const double*)c->coef64, part);
+    bdg_status st = hip_check(c, hipGetLastError(), "k_coef_bound");
+    double hp[NB];
+    if (st == BDG_OK) st = d2h(c, hp, part, NB * sizeof(double));
+    ctx_free(c, part);
+    if (st != BDG_OK) return st;
+    double mx = 0;
+    for (int i = 0; i < NB; ++i) mx = std::max(mx, hp[i]);
+    *out = kin + mx;
+    return BDG_OK;
+}
 
 bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const void* X0_dev,
                      unsigned long long seed, double* omega_out, void* UV_dev, double* res_out, int* iters_out) {
@@ -702,6 +765,8 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     double* d_n = dvec + nb;      // 4 nb norms
     // ------------------------------------------------------------------ deflation
     BDG_TRY(build_deflation(c, w, D, opt.null_tol));
+    double hbound = 0;
+    BDG_TRY(operator_bound(c, &hbound));
     auto t_setup = std::chrono::steady_clock::now();
     c->stats[6] = std::chrono::duration<double, std::milli>(t_setup - t_start).count();
     // ------------------------------------------------------------------ start block
@@ -728,6 +793,8 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     double2* Mr = w.buf[3];
     double2* Kr = w.buf[4];
     std::vector<double> om;
+    // per-column target: tol, or the rounding floor of the relative residual when that is larger
+    auto target = [&](int j) { return std::max(tol, opt.floor_c * DBL_EPSILON * hbound / std::fabs(om[j])); };
     auto grams = [&](const Seg* sf, const Seg* sg, const Seg* hf, const Seg* hg, int ns, int ldc) -> bdg_status {
         BDG_TRY(gram_seg(c, nh, sf, ns, nh, sf, ns, nh, c->hd, Gf, ldc, 1));
         BDG_TRY(gram_seg(c, nh, sg, ns, nh, sg, ns, nh, c->hd, Gg, ldc, 1));
@@ -799,11 +866,13 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         BDG_TRY(resnorm2(c, nh, nb, HF, G, HG, F, nh, d_om, d_n));
         BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
         double rmax = 0;
+        bool all_k = true;
         act.clear();
         for (int j = 0; j < nb; ++j) {
             res[j] = std::sqrt(hn[j] + hn[nb + j]) / (std::fabs(om[j]) * std::sqrt(hn[2 * nb + j] + hn[3 * nb + j]));
-            if (j < k) rmax = std::max(rmax, res[j]);
-            if (!(res[j] <= tol)) act.push_back(j);      // soft locking: converged columns get no correction
+            const bool done = res[j] <= target(j);
+            if (j < k) { rmax = std::max(rmax, res[j]); all_k = all_k && done; }
+            if (!done) act.push_back(j);      // soft locking: converged columns get no correction
         }
         const int nact = (int)act.size();
         if (!(rmax == rmax)) return ctx_fail(c, BDG_EBREAKDOWN, "non-finite residual");
@@ -834,7 +903,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             --it;
             continue;
         }
-        if (rmax <= tol || nact == 0) {
+        if (all_k || nact == 0) {
             // certify with a float64 apply of the current block
             double2* CF = S.col(HSF, S.slotFree);
             double2* CG = S.col(HSG, S.slotFree);
@@ -842,12 +911,12 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             napply64 += nb;
             BDG_TRY(resnorm2(c, nh, nb, CF, G, CG, F, nh, d_om, d_n));
             BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
-            double cmax = 0;
+            bool certified = true;
             for (int j = 0; j < nb; ++j) {
                 res[j] = std::sqrt(hn[j] + hn[nb + j]) / (std::fabs(om[j]) * std::sqrt(hn[2 * nb + j] + hn[3 * nb + j]));
-                if (j < k) cmax = std::max(cmax, res[j]);
+                if (j < k) certified = certified && res[j] <= target(j);
             }
-            if (cmax <= tol) {
+            if (certified) {
                 converged = true;
                 break;
             }
@@ -920,6 +989,14 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             napply32 += nact;
         } else {
             BDG_TRY(apply64(c, nact, Wf, Wg, nh, HWf, HWg));
+            napply64 += nact;
+        }
+        // with float64 images, P's images are recomputed from P: the recurrence [H W, H P] a
+        // carries the cancellation in P = [W, P] a (a short step built from unit columns) into
+        // the images, whose relative error then grows by the convergence factor per iteration
+        if (S.slotP >= 0 && !(mixed && !force64)) {
+            BDG_TRY(apply64(c, nact, S.col(SF, S.slotP), S.col(SG, S.slotP), nh, S.col(HSF, S.slotP),
+                            S.col(HSG, S.slotP)));
             napply64 += nact;
         }
         BDG_TRY(sync_if());

@@ -44,7 +44,7 @@ def _problem(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(dim=0), dict(dim=4), dict(n=(30, 32, 1)), dict(n=(4, 32, 1)),
-                                 dict(n=(1024, 32, 1)), dict(L=(0.0, 4.0, 1.0)), dict(mass=0.0),
+                                 dict(n=(2048, 32, 1)), dict(L=(0.0, 4.0, 1.0)), dict(mass=0.0),
                                  dict(M=1.0), dict(M=-1.5), dict(beta_n=float("nan")), dict(precision=7)])
 def test_create_rejects_invalid_problem(bad):
     from paper_2506_08308_amd import _lib

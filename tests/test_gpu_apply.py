@@ -16,6 +16,10 @@ CASES = [
     W.Workload("3d_32_afm", 3, (32, 32, 32), (5.0, 5.0, 5.0), "harmonic3", 30.0, 1.5, 0.3),
     W.Workload("1d_512_fm", 1, (512,), (16.0,), "harmonic1", 10.0, -0.5, 0.2),
     W.Workload("2d_8x256_fm", 2, (8, 256), (3.0, 12.0), "harmonic2", 10.0, -0.5, 0.0),
+    # 1024-point axes: the final x pass runs each thread over two of the six fields
+    W.Workload("1d_1024_fm", 1, (1024,), (32.0,), "harmonic1", 10.0, -0.5, 0.2),
+    W.Workload("2d_1024x8_fm", 2, (1024, 8), (24.0, 3.0), "harmonic2", 10.0, -0.5, 0.1),
+    W.Workload("2d_8x1024_polar", 2, (8, 1024), (3.0, 24.0), "harmonic2", 10.0, 1.0, 0.0),
 ]
 
 
@@ -53,7 +57,7 @@ def test_apply_fp64_matches_oracle(w, form, transpose):
     ctx.close()
 
 
-@pytest.mark.parametrize("w", CASES[:5], ids=lambda w: w.name)
+@pytest.mark.parametrize("w", CASES[:5] + CASES[7:], ids=lambda w: w.name)
 def test_apply_fp32_matches_oracle(w):
     torch = torch_cuda()
     from paper_2506_08308_amd import Form, Precision

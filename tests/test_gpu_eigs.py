@@ -122,3 +122,25 @@ def test_ground_state_matches_oracle():
         assert np.abs(phi.cpu().numpy() - r.phi).max() < 1e-10
         assert np.allclose(mu, r.mu, atol=1e-10)
         ctx.close()
+
+
+def test_1024_point_axis_eigs_match_branch_decomposition():
+    """1-D FM trap on 1024 points (the largest axis): the spectrum equals the oracle's scalar
+    branch decomposition, and the GPU ground state equals the oracle flow."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Precision
+    w = W.Workload("1d_1024_fm", 1, (1024,), (32.0,), "harmonic1", 10.0, -0.5, 0.2, k=16, block=24)
+    say("eigs", w.name)
+    V, r, coef = oracle_ground(w)
+    M = w.magnetization
+    phi = np.tensordot(np.array([(1 + M) / 2, np.sqrt((1 - M * M) / 2), (1 - M) / 2]), r.phi, axes=1)
+    ref = branch.fm_spectrum_dense(phi, r.mu[0], V, w.beta_n, w.beta_s, w.n, w.L, w.k)
+    ctx = make_ctx(w, Precision.FP64, V)
+    g_phi, g_mu, g_res, g_its = ctx.ground_state(tol=1e-12, max_iter=200000)
+    say("   ground state iters", g_its, "res", g_res)
+    assert np.abs(g_phi.cpu().numpy() - r.phi).max() < 1e-9
+    ctx.set_ground_state(torch.from_numpy(r.phi), r.mu)
+    out = ctx.eigs(w.k, w.block, tol=1e-10, max_iter=3000, seed=3)
+    say("   iters", out["iters"])
+    assert np.allclose(out["omega"], ref, rtol=1e-9)
+    ctx.close()
