@@ -308,8 +308,11 @@ def campaign_accuracy(k=40, block=48, dims=(1, 2, 3)):
                     out = ctx.eigs(kk, bb, tol=1e-10, max_iter=1500, seed=0, check=False)
                     if max(out["omega"]) > 1.05 * max(W.TRAP_GAMMAS[pot]) or kk >= 148:
                         break
-                    bb = min(min(2 * kk, 148) + 12, 3 * w.npts - 4)
-                    kk = min(2 * kk, 148, bb)
+                    # basis memory: 4 arrays x 4 slots x block x 3 npts complex128 <= 160 GB
+                    bb = min(min(2 * kk, 148) + 12, 3 * w.npts - 4, int(160e9 / (256 * 3 * w.npts)))
+                    if bb <= kk:
+                        break
+                    kk = min(2 * kk, 148, bb - 8)
                 torch.cuda.synchronize()
                 errs = _kohn_errors(w, phi.cpu().numpy(), out["omega"], out["uv"].cpu().numpy(),
                                     W.TRAP_GAMMAS[pot])

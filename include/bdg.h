@@ -116,10 +116,13 @@ bdg_status bdg_biortho(bdg_ctx* ctx, int nvec, void* F_dev, void* G_dev, double*
  * (Section 2.3), bi-orthogonal Gram-Schmidt and Rayleigh-Ritz projection.  Corrections
  * use the kinetic-potential preconditioner D (|k|^2/2 + sigma)^-1 D with
  * sigma = max(mu_0 / 2, 1/2) and D^2 = sigma / (sigma + max(V - mu_0, 0)) (mu_0: the
- * middle chemical potential); columns whose residual is already <= tol get no correction
- * (soft locking).  Converged when every wanted column has
- *   res_j = ||(H_- g_j - w_j f_j, H_+ f_j - w_j g_j)|| / (|w_j| ||(f_j, g_j)||) <= tol,
- * checked with a float64 apply at the end.
+ * middle chemical potential); columns whose residual already meets its target get no
+ * correction (soft locking).  Converged when every wanted column has
+ *   res_j = ||(H_- g_j - w_j f_j, H_+ f_j - w_j g_j)|| / (|w_j| ||(f_j, g_j)||)
+ *         <= max(tol, 100 eps ||H|| / |w_j|),
+ * checked with a float64 apply at the end; the second term is the float64 rounding floor of
+ * this relative residual (eps = DBL_EPSILON, ||H|| bounded by the largest kinetic symbol plus
+ * the largest pointwise row sum of H_+-), so `residual` may exceed a tol below that floor.
  * X0_dev: block x 6 npts complex128 start block in (f, g) form (NULL = complex normal
  * block drawn from `seed`).  omega (host, k): ascending; UV_dev (device, k x 6 npts
  * complex128): eigenvectors in (u, v) form with int |u|^2 - |v|^2 = 1 (i.e. <f, g> = 1/4);

@@ -9,7 +9,8 @@
 //   residual   R = H_+ F - G diag(w) (f-direction), H_- G - F diag(w) (g-direction);
 //   correction W = D (|k|^2/2 + sigma)^-1 D R (kinetic-potential preconditioner, D^2 =
 //              sigma / (sigma + max(V - mu_0, 0)), sigma = max(mu_0 / 2, 1/2)) for the active
-//              columns only (res > tol; converged columns are soft-locked), projected off
+//              columns only (res above max(tol, 100 eps ||H|| / |w|), the float64 floor
+//              of the relative residual; converged columns are soft-locked), projected off
 //              the generalized nullspace (f orthogonal to ns(H_-), g orthogonal to
 //              ns(H_+) + Jordan partners);
 //   projection each basis is made orthonormal on its own by a pivoted Cholesky of its
@@ -24,7 +25,9 @@
 //              a = L_K u, b = L_M v;
 //   update     P <- [W, P] a_{W,P} (and images), then F <- F a_F + P, G likewise with b;
 //              W and P keep their raw scale, their unit-column scaling enters the Gram
-//              matrices and the coefficient rows.
+//              matrices and the coefficient rows.  With float64 images, H P is recomputed
+//              from P before each projection (the recurrence image of the short step P
+//              loses relative accuracy by the inverse convergence factor per iteration).
 // Gram matrices and updates run on the FP64 matrix cores; the projected problems on the
 // device in FP64; the host only reads back residual norms and small singular values.
 #include "common.h"
