@@ -350,6 +350,44 @@ def campaign_efficiency(k=40, block=48, tol=1e-8, dims=(2, 3)):
                       flush=True)
 
 
+# Section 4.2, Example "2D Case": perturbed densities n_j^l(x, t = 10.6) with eps = 0.1 at
+# h = 1/8 on [-16, 16]^2; Case I antiferromagnetic isotropic (l = 20, 35), Case II
+# ferromagnetic with gamma_y = 2 gamma_x (l = 30, 55); l counts the ascending eigenvalues from 1.
+MODES_CASES = [("I", "harmonic2", "AFM", (20, 35)), ("II", "harmonic2_aniso", "FM", (30, 55))]
+
+
+def campaign_modes(n=256, k=56, block=64, eps=0.1, t_snap=10.6):
+    import torch
+    for case, pot, kind, ells in MODES_CASES:
+        bn, bs = CAMPAIGN_BETAS[kind]
+        w = W.Workload(f"modes_{case}_{kind}_{n}", 2, (n, n), (16.0, 16.0), pot, bn, bs, 0.0, k=k, block=block)
+        log(f"modes {w.name}")
+        ctx = _context(w)
+        phi, mu, gres, gits = _ground_state(ctx)
+        out = ctx.eigs(k, block, tol=1e-9, max_iter=1500, seed=0, check=False)
+        hd = float(np.prod(w.h))
+        sel = [l - 1 for l in ells]
+        dens = ctx.perturbed_density([out["omega"][j] for j in sel], out["uv"][sel], eps, [t_snap]).cpu().numpy()
+        rho0 = hd * (phi.cpu().numpy() ** 2).sum(axis=(1, 2))
+        snaps = []
+        for i, l in enumerate(ells):
+            nj = dens[i, 0]
+            snaps.append({"l": l, "omega": out["omega"][l - 1], "norm_j": (hd * nj.sum(axis=(1, 2))).tolist(),
+                          "max_j": nj.max(axis=(1, 2)).tolist()})
+        # bandwidth of the density kernel: all k modes at 16 times
+        times = list(np.linspace(0.0, t_snap, 16))
+        ms = _event_ms(ctx.stream, lambda: ctx.perturbed_density(out["omega"], out["uv"], eps, times), 5)
+        nbytes = k * (6 * w.npts * 16 + 3 * w.npts * 8) + k * len(times) * 3 * w.npts * 8
+        ctx.close()
+        print(json.dumps({"campaign": "modes", "case": case, "kind": kind, "N": n, "eps": eps, "t": t_snap,
+                          "eig_status": out["status"], "eig_iters": out["iters"], "ground_norm_j": rho0.tolist(),
+                          "snapshots": snaps,
+                          "density_kernel": {"modes": k, "times": len(times), "ms": round(ms, 4),
+                                             "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                             "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}}),
+              flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,8 +398,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 solve timed beside the mixed one")
     ap.add_argument("--kernels-only", action="store_true")
-    ap.add_argument("--campaign", choices=("accuracy", "efficiency"),
-                    help="the paper's accuracy (Kohn modes vs h) or efficiency (time vs DOF) campaign")
+    ap.add_argument("--campaign", choices=("accuracy", "efficiency", "modes"),
+                    help="the paper's accuracy (Kohn modes vs h) or efficiency (time vs DOF) campaign, or its "
+                         "perturbed-density example")
     ap.add_argument("--campaign-dims", default="1,2,3", help="comma-separated dimensions to run")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -382,6 +421,9 @@ def main():
         return
     if args.campaign == "efficiency":
         campaign_efficiency(dims=dims)
+        return
+    if args.campaign == "modes":
+        campaign_modes()
         return
     X0 = torch.from_numpy(W.start_block(w)).to("cuda")
     ctx, out, times, gs_s = solve(w, X0, args.steps, args.warmup, args.max_iter)

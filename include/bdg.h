@@ -148,6 +148,18 @@ bdg_status bdg_eigs(bdg_ctx* ctx, int k, int block, double tol, int max_iter,
 bdg_status bdg_eigs_grad(bdg_ctx* ctx, int k, const double* omega, const void* UV_dev,
                          double* dV_dev, double* dbeta_n, double* dbeta_s);
 
+/* Perturbed densities of normal modes (Section 4.2, Applications; the perturbed-density
+ * formula used to visualize an excitation): for nmodes eigenpairs and nt times,
+ *   n_j^l(x, t_s) = |phi_j(x) + eps (u_j^l(x) e^{-i omega_l t_s} + conj(v_j^l(x)) e^{i omega_l t_s})|^2,
+ * j = 1, 0, -1, with Phi the context's ground state.  omega (host, nmodes) and t (host, nt);
+ * UV_dev (device, nmodes x 6 npts complex128): the (u, v) vectors as bdg_eigs returns them;
+ * out_dev (device, nmodes x nt x 3 npts float64, mode-major, then time, then component).
+ * The caller owns every buffer.  nmodes = 0 or nt = 0 is a no-op; BDG_EINVAL on negative
+ * counts, null pointers or non-finite omega, t, eps; BDG_ESTATE without a ground state.
+ * Synchronizes the context stream before returning. */
+bdg_status bdg_perturbed_density(bdg_ctx* ctx, int nmodes, const double* omega, const void* UV_dev,
+                                 double eps, int nt, const double* t, void* out_dev);
+
 /* Per-phase timers and counters of the last bdg_eigs call (milliseconds from HIP events):
  * out[0] total, out[1] apply, out[2] preconditioner, out[3] Gram matrices, out[4] small
  * dense solves, out[5] basis updates, out[6] setup (deflation), out[7] iterations,

@@ -182,6 +182,19 @@ class BdgContext:
                                             ctypes.c_void_p(_ptr(dV)), dbn, dbs), "bdg_eigs_grad")
         return dV, list(dbn), list(dbs)
 
+    def perturbed_density(self, omega, uv, eps, t):
+        """n_j^l(x, t_s) = |phi_j + eps (u_j^l e^{-i w_l t_s} + conj(v_j^l) e^{i w_l t_s})|^2 for the
+        modes (omega, uv as eigs returns them) and times t; shape (nmodes, nt, 3, *grid)."""
+        torch = _torch()
+        nm, nt = len(omega), len(t)
+        out = torch.empty((nm, nt, 3) + self.grid_shape, dtype=torch.float64, device=self.device)
+        om = (ctypes.c_double * max(nm, 1))(*[float(v) for v in omega])
+        ts = (ctypes.c_double * max(nt, 1))(*[float(v) for v in t])
+        u = uv.to(dtype=torch.complex128).contiguous() if nm else None
+        self._check(self._lib.bdg_perturbed_density(self._h, nm, om, ctypes.c_void_p(_ptr(u)), float(eps), nt, ts,
+                                                    ctypes.c_void_p(_ptr(out))), "bdg_perturbed_density")
+        return out
+
     def stats(self):
         out = (ctypes.c_double * 10)()
         self._check(self._lib.bdg_stats(self._h, out, 10), "bdg_stats")

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbdg.so")
-SOURCES = ["capi.hip", "fft_apply.hip", "dense.hip", "smalldense.hip", "solver.hip", "gs.hip"]
+SOURCES = ["capi.hip", "fft_apply.hip", "dense.hip", "smalldense.hip", "solver.hip", "gs.hip", "modes.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep float32 arithmetic out of the packed (v_pk_*_f32) forms
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
