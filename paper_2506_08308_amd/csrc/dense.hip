@@ -39,7 +39,11 @@ __device__ __forceinline__ const double2* seg_col(const SegList& sl, int col, lo
 constexpr int GT = 64;          // output tile edge
 constexpr int GKC = 16;         // complex rows per LDS chunk (32 real rows)
 constexpr int GKR = 2 * GKC;
-constexpr int GPAD = GKR + 1;   // LDS row pitch in doubles (bank spread)
+// LDS pitch of a staged column in doubles.  A fragment read has lane l at column l % 16 and
+// real row l / 16; with a pitch of 2 mod 32 each half-wave's 32 doubles fall on 64 distinct
+// 4-byte banks (a pitch of 33 put two lanes on each bank pair: 40 % of the LDS cycles were
+// bank conflicts), and an even pitch keeps the complex pairs 16-byte aligned for b128 stores.
+constexpr int GPAD = GKR + 2;
 
 // Work item -> (split, tile).  Workgroups are dispatched to the 8 XCDs round-robin by linear
 // id, so item w = (id % 8) * per_xcd + id / 8 gives every XCD a contiguous run of items: all
@@ -71,8 +75,8 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
                                               long long ldb, long long kper, int tn, int herm, int same,
                                               int ntiles, long long total, long long per_xcd,
                                               double2* __restrict__ part) {
-    __shared__ double la[GT * GPAD];
-    __shared__ double lb[GT * GPAD];
+    __shared__ __align__(16) double la[GT * GPAD];
+    __shared__ __align__(16) double lb[GT * GPAD];
     long long split;
     int ti, tj;
     if (!gram_item(blockIdx.x, per_xcd, total, ntiles, tn, herm, &split, &ti, &tj)) return;
@@ -120,12 +124,8 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
 #pragma unroll
         for (int pass = 0; pass < 4; ++pass) {
             const int col = lc + 16 * pass;
-            la[col * GPAD + 2 * lk] = ra[pass].x;
-            la[col * GPAD + 2 * lk + 1] = ra[pass].y;
-            if (!diag) {
-                lb[col * GPAD + 2 * lk] = rb[pass].x;
-                lb[col * GPAD + 2 * lk + 1] = rb[pass].y;
-            }
+            *reinterpret_cast<double2*>(&la[col * GPAD + 2 * lk]) = ra[pass];
+            if (!diag) *reinterpret_cast<double2*>(&lb[col * GPAD + 2 * lk]) = rb[pass];
         }
         __syncthreads();
         if (kc + GKC < k1) gload(kc + GKC);
