@@ -132,3 +132,31 @@ def test_solves_are_bitwise_deterministic():
     X = torch.from_numpy(W.random_block((3, 6) + w.shape, seed=2)).to("cuda")
     assert torch.equal(ctx.apply(X, Form.FG), ctx.apply(X, Form.FG))
     ctx.close()
+
+
+def test_tolerance_below_the_rounding_floor():
+    """tol = 1e-15 is below the float64 floor eps ||H|| / omega of the relative residual for
+    the ferromagnetic spin modes (omega ~ 0.02): every column stops at
+    max(tol, 100 eps ||H|| / omega_j) with status OK, and the spectrum equals the oracle's
+    dense eigensolve of the same ground state."""
+    torch = torch_cuda()
+    w = W.Workload("1d_128_fm_m0", 1, (128,), (16.0,), "harmonic1", 885.4, -4.1, 0.0)
+    say("rounding floor", w.name)
+    V = W.potential(w)
+    ctx = make_ctx(w, None, V)
+    phi, mu, res, its = ctx.ground_state(tol=1e-12, max_iter=400000)
+    out = ctx.eigs(12, 16, tol=1e-15, max_iter=1500, seed=2)
+    coef = bdg.coefficients(phi.cpu().numpy(), np.array(mu), V, w.beta_n, w.beta_s)
+    om_d, _ = bdg.positive_eigs_dense(bdg.dense_uv(coef, w.n, w.L), 12)
+    # the operator bound the library uses: largest kinetic symbol + largest pointwise row sum
+    kin = 0.5 * (np.pi * 128 / 32.0) ** 2
+    Hp, Hm = bdg.hpm(coef)
+    rows = max(np.abs(Hp).sum(axis=1).max(), np.abs(Hm).sum(axis=1).max())
+    floor = 100 * np.finfo(float).eps * (kin + rows) / np.array(out["omega"])
+    res = np.array(out["residual"])
+    say(f"   iters {out['iters']}, residuals {res.min():.1e}..{res.max():.1e}, floors {floor.min():.1e}..{floor.max():.1e}")
+    assert out["status"] == 0
+    assert np.all(res <= floor * 1.01)
+    assert np.any(res > 1e-15)
+    assert np.allclose(out["omega"], om_d, rtol=1e-10)
+    ctx.close()
