@@ -91,6 +91,17 @@ bdg_status bdg_ground_state(bdg_ctx* ctx, const double* phi0_dev, double tol, in
  * potentials; builds the pointwise coefficient fields of H_+ = A + B and H_- = A - B. */
 bdg_status bdg_set_ground_state(bdg_ctx* ctx, const double* phi_dev, const double mu[3]);
 
+/* Install a complex ground state (the general BdG form of Section 2.1: A complex Hermitian,
+ * B complex symmetric, H = [[A, B], [-conj B, -conj A]]; e.g. vortex or moving states).
+ * phi_dev: 3 npts complex128 (device, copied; components 1, 0, -1); mu[3] (host): the
+ * chemical potentials (the caller's state must be stationary with them, as for
+ * bdg_set_ground_state).  Needs a BDG_FP64 context (BDG_EINVAL otherwise).  Afterwards
+ * bdg_apply takes the (u, v) form without transpose, bdg_eigs solves H x = w x through the
+ * Hermitian pencil sigma_3 x = (1/w) K x, K = sigma_3 H, and bdg_perturbed_density uses the
+ * complex Phi; bdg_eigs_grad returns BDG_EINVAL.  bdg_ground_state or bdg_set_ground_state
+ * return the context to a real ground state. */
+bdg_status bdg_set_ground_state_complex(bdg_ctx* ctx, const void* phi_dev, const double mu[3]);
+
 /* Block application of the BdG operator (Section 3.1, eqs. BdG-d / lrep-d; matrix-free
  * product of Section 3.2: forward FFT, kinetic multiplier |k|^2/2, inverse FFT, pointwise
  * 3x3 coupling in physical space).

@@ -24,4 +24,4 @@ Bogoliubov-de Gennes excitation eigenvalue problem", arXiv 2506.08308):
 Parity status of each function is stated in its module header; a function
 without an independent pin says "parity unpinned".
 """
-from . import spectral, spin, groundstate, bdg, branch, lrep, grad, kohn, modes  # noqa: F401
+from . import spectral, spin, groundstate, bdg, branch, lrep, grad, kohn, modes, complexgs  # noqa: F401

@@ -16,9 +16,9 @@ import numpy as np
 
 
 def perturbed_density(phi, uv, omega, eps, t):
-    """phi (3, *grid) real; uv (nmodes, 6, *grid) complex (u then v); omega (nmodes,); t (nt,).
-    Returns (nmodes, nt, 3, *grid) float64."""
-    phi = np.asarray(phi, dtype=np.float64)
+    """phi (3, *grid) real or complex; uv (nmodes, 6, *grid) complex (u then v); omega (nmodes,);
+    t (nt,).  Returns (nmodes, nt, 3, *grid) float64."""
+    phi = np.asarray(phi)
     uv = np.asarray(uv, dtype=np.complex128)
     omega = np.asarray(omega, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)

@@ -13,7 +13,8 @@ BDG_FP64, BDG_FP32_APPLY = 0, 1
 BDG_FORM_UV, BDG_FORM_FG = 0, 1
 
 EXPORTS = ("bdg_create", "bdg_destroy", "bdg_last_error", "bdg_ground_state", "bdg_set_ground_state",
-           "bdg_apply", "bdg_biortho", "bdg_eigs", "bdg_eigs_grad", "bdg_perturbed_density", "bdg_stats",
+           "bdg_set_ground_state_complex", "bdg_apply", "bdg_biortho", "bdg_eigs", "bdg_eigs_grad",
+           "bdg_perturbed_density", "bdg_stats",
            "bdg_test_gram", "bdg_test_update", "bdg_test_svd", "bdg_test_cholesky", "bdg_test_pchol",
            "bdg_test_plu")
 
@@ -55,6 +56,8 @@ def load() -> ctypes.CDLL:
     lib.bdg_eigs.restype = st
     lib.bdg_eigs_grad.argtypes = [vp, i, pd, vp, vp, pd, pd]
     lib.bdg_eigs_grad.restype = st
+    lib.bdg_set_ground_state_complex.argtypes = [vp, vp, pd]
+    lib.bdg_set_ground_state_complex.restype = st
     lib.bdg_perturbed_density.argtypes = [vp, i, pd, vp, d, i, pd, vp]
     lib.bdg_perturbed_density.restype = st
     lib.bdg_stats.argtypes = [vp, pd, i]

@@ -130,6 +130,14 @@ class BdgContext:
         self._check(self._lib.bdg_set_ground_state(self._h, ctypes.c_void_p(_ptr(self._phi)), m),
                     "bdg_set_ground_state")
 
+    def set_ground_state_complex(self, phi, mu):
+        """Install a complex ground state (3, *grid) complex128 with chemical potentials mu."""
+        torch = _torch()
+        self._phic = phi.to(device=self.device, dtype=torch.complex128).contiguous()
+        m = (ctypes.c_double * 3)(*[float(v) for v in mu])
+        self._check(self._lib.bdg_set_ground_state_complex(self._h, ctypes.c_void_p(_ptr(self._phic)), m),
+                    "bdg_set_ground_state_complex")
+
     def apply(self, X, form: Form = Form.FG, transpose: bool = False, out=None):
         """Y = H X for a block X of shape (b, 6, *grid) (complex128, or complex64 in FP32_APPLY)."""
         torch = _torch()

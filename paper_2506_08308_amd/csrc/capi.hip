@@ -124,6 +124,75 @@ __global__ void k_coef(long long npts, const double* __restrict__ V, const doubl
     }
 }
 
+// Complex ground state: A = (V - Lambda) I + beta_n (rho I + Phi Phi^H)
+// + beta_s (S.s + sum_j (S_j Phi)(S_j Phi)^H) and B = beta_n Phi Phi^T + beta_s sum_j (S_j Phi)(S_j Phi)^T
+// (eqs. def_A, def_B with s = Phi^H S Phi), stored as the 21 fields described in common.h.
+__device__ __forceinline__ double2 cm(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ double2 cj(double2 a) { return double2{a.x, -a.y}; }
+
+__global__ void k_coef_complex(long long npts, const double* __restrict__ V, const double2* __restrict__ phi,
+                               double mu1, double mu0, double mum, double bn, double bs, double* __restrict__ cc,
+                               double ps, double* __restrict__ w64, float* __restrict__ w32) {
+    const double r2 = 0.70710678118654752440;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
+         p += (long long)gridDim.x * blockDim.x) {
+        const double2 f[3] = {phi[p], phi[npts + p], phi[2 * npts + p]};
+        // S_j Phi, j = x, y, z (S_y = i/sqrt2 [[0, -1, 0], [1, 0, -1], [0, 1, 0]])
+        double2 v[3][3];
+        v[0][0] = double2{r2 * f[1].x, r2 * f[1].y};
+        v[0][1] = double2{r2 * (f[0].x + f[2].x), r2 * (f[0].y + f[2].y)};
+        v[0][2] = v[0][0];
+        v[1][0] = double2{r2 * f[1].y, -r2 * f[1].x};                           // -i b / sqrt2
+        v[1][1] = double2{-r2 * (f[0].y - f[2].y), r2 * (f[0].x - f[2].x)};     // i (a - d) / sqrt2
+        v[1][2] = double2{-r2 * f[1].y, r2 * f[1].x};                           // i b / sqrt2
+        v[2][0] = f[0];
+        v[2][1] = double2{0, 0};
+        v[2][2] = double2{-f[2].x, -f[2].y};
+        double s[3], rho = 0;
+        for (int c = 0; c < 3; ++c) rho += f[c].x * f[c].x + f[c].y * f[c].y;
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int c = 0; c < 3; ++c) acc += f[c].x * v[j][c].x + f[c].y * v[j][c].y;   // Re conj(f) . v
+            s[j] = acc;
+        }
+        const double2 sm = double2{r2 * s[0], -r2 * s[1]};     // (s_x - i s_y) / sqrt2: (S.s)_01 = (S.s)_12
+        double2 A[3][3], B[3][3];
+        const double lam[3] = {mu1, mu0, mum};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double2 x = cm(f[a], cj(f[b]));
+                double2 y = cm(f[a], f[b]);
+                double2 av = double2{bn * x.x, bn * x.y}, bv = double2{bn * y.x, bn * y.y};
+                for (int j = 0; j < 3; ++j) {
+                    const double2 xa = cm(v[j][a], cj(v[j][b])), ya = cm(v[j][a], v[j][b]);
+                    av.x += bs * xa.x; av.y += bs * xa.y;
+                    bv.x += bs * ya.x; bv.y += bs * ya.y;
+                }
+                A[a][b] = av;
+                B[a][b] = bv;
+            }
+        for (int a = 0; a < 3; ++a) A[a][a].x += V[p] - lam[a] + bn * rho;
+        A[0][0].x += bs * s[2];
+        A[2][2].x -= bs * s[2];
+        A[0][1].x += bs * sm.x; A[0][1].y += bs * sm.y;
+        A[1][2].x += bs * sm.x; A[1][2].y += bs * sm.y;
+        double* o = cc + p;
+        o[0] = A[0][0].x; o[npts] = A[1][1].x; o[2 * npts] = A[2][2].x;
+        o[3 * npts] = A[0][1].x; o[4 * npts] = A[0][1].y;
+        o[5 * npts] = A[0][2].x; o[6 * npts] = A[0][2].y;
+        o[7 * npts] = A[1][2].x; o[8 * npts] = A[1][2].y;
+        const int bi[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+        for (int e = 0; e < 6; ++e) {
+            o[(9 + 2 * e) * npts] = B[bi[e][0]][bi[e][1]].x;
+            o[(10 + 2 * e) * npts] = B[bi[e][0]][bi[e][1]].y;
+        }
+        const double u = V[p] - mu0 > 0.0 ? V[p] - mu0 : 0.0;
+        const double dw = sqrt(ps / (ps + u));
+        w64[p] = dw;
+        w32[p] = (float)dw;
+    }
+}
+
 }  // namespace
 
 bdg_status build_coefficients(bdg_ctx* c) {
@@ -258,6 +327,32 @@ bdg_status bdg_set_ground_state(bdg_ctx* c, const double* phi_dev, const double 
     BDG_TRY(build_coefficients(c));
     BDG_HIP(c, hipStreamSynchronize(c->stream));
     c->has_gs = true;
+    c->complex_gs = false;
+    return BDG_OK;
+}
+
+bdg_status bdg_set_ground_state_complex(bdg_ctx* c, const void* phi_dev, const double mu[3]) {
+    if (!c) return BDG_EINVAL;
+    if (!phi_dev || !mu) return ctx_fail(c, BDG_EINVAL, "bdg_set_ground_state_complex: null argument");
+    if (c->prob.precision != BDG_FP64)
+        return ctx_fail(c, BDG_EINVAL, "bdg_set_ground_state_complex: needs a BDG_FP64 context");
+    for (int j = 0; j < 3; ++j)
+        if (!std::isfinite(mu[j])) return ctx_fail(c, BDG_EINVAL, "bdg_set_ground_state_complex: non-finite mu");
+    const long long n = c->npts;
+    if (!c->phic) BDG_TRY(ctx_alloc(c, (void**)&c->phic, 3 * n * sizeof(double2)));
+    if (!c->ccoef) BDG_TRY(ctx_alloc(c, (void**)&c->ccoef, 21 * n * sizeof(double)));
+    if (phi_dev != c->phic)
+        BDG_HIP(c, hipMemcpyAsync(c->phic, phi_dev, 3 * n * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    for (int j = 0; j < 3; ++j) c->mu[j] = mu[j];
+    c->pshift = std::max(0.5 * c->mu[1], 0.5);
+    const int blocks = (int)std::min<long long>(4096, (n + 255) / 256);
+    const bdg_problem& pr = c->prob;
+    hipLaunchKernelGGL(k_coef_complex, dim3(blocks), dim3(256), 0, c->stream, n, c->V, (const double2*)c->phic,
+                       c->mu[0], c->mu[1], c->mu[2], pr.beta_n, pr.beta_s, c->ccoef, c->pshift, c->pw64, c->pw32);
+    BDG_TRY(hip_check(c, hipGetLastError(), "k_coef_complex"));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    c->has_gs = true;
+    c->complex_gs = true;
     return BDG_OK;
 }
 
@@ -269,6 +364,8 @@ bdg_status bdg_apply(bdg_ctx* c, int form, int transpose, int nvec, const void* 
     if (nvec == 0) return BDG_OK;
     if (!X || !Y) return ctx_fail(c, BDG_EINVAL, "bdg_apply: null pointer");
     if (!c->has_gs) return ctx_fail(c, BDG_ESTATE, "bdg_apply: no ground state set");
+    if (c->complex_gs && (form != BDG_FORM_UV || transpose != 0))
+        return ctx_fail(c, BDG_EINVAL, "bdg_apply: a complex ground state takes the (u, v) form, no transpose");
     const bool f32 = c->prob.precision == BDG_FP32_APPLY;
     const size_t bytes = (size_t)nvec * 6 * c->npts * (f32 ? sizeof(float2) : sizeof(double2));
     const char* xa = (const char*)X;
@@ -282,6 +379,7 @@ bdg_status bdg_apply(bdg_ctx* c, int form, int transpose, int nvec, const void* 
     }
     BlockRef<const double2> xr{(const double2*)X, (const double2*)X + 3 * c->npts, vs};
     BlockRef<double2> yr{(double2*)Y, (double2*)Y + 3 * c->npts, vs};
+    if (c->complex_gs) return launch_apply_complex(c, 0, nvec, xr, yr);
     return launch_apply<double>(c, form, transpose, nvec, xr, yr);
 }
 

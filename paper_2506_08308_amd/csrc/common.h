@@ -53,6 +53,12 @@ struct bdg_ctx {
     double* phi = nullptr;        // 3 npts (ground state)
     double mu[3] = {0, 0, 0};
     bool has_gs = false;
+    // complex ground state (general BdG form [[A, B], [-conj B, -conj A]]): the spinor and
+    // 21 real fields per point, A's real diagonal (3), A's upper entries 01, 02, 12 (re, im),
+    // then B's symmetric entries 00, 01, 02, 11, 12, 22 (re, im); V - mu folded into A
+    bool complex_gs = false;
+    double2* phic = nullptr;      // 3 npts
+    double* ccoef = nullptr;      // 21 npts
     double* coef64 = nullptr;     // 12 npts: H_+ (6 sym entries) then H_- (6), V - mu folded in
     float* coef32 = nullptr;      // same, rounded
     // kinetic-potential preconditioner D (|k|^2/2 + pshift)^-1 D of the eigensolver:
@@ -116,6 +122,10 @@ bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
 // Mixed form of launch_precond on nvec (f, g) pairs: float32 passes in place on X32 (lo: the
 // f halves, hi: the g halves, vector stride vstride), the last pass writes float64 into Y64.
 bdg_status launch_precond_mixed(bdg_ctx* c, int nvec, BlockRef<float2> X32, BlockRef<double2> Y64);
+// complex ground state, (u, v) vectors in float64: kform = 0 gives Y = H X with
+// H = [[T + A, B], [-conj B, -(T + conj A)]]; kform = 1 gives Y = sigma_3 H X, i.e. the
+// Hermitian positive semidefinite K = [[T + A, B], [conj B, T + conj A]]
+bdg_status launch_apply_complex(bdg_ctx* c, int kform, int nvec, BlockRef<const double2> X, BlockRef<double2> Y);
 
 // Y = D F^-1 m(k) F D X with m = |k|^2/2 (precond = 0) or (|k|^2/2 + shift)^-1
 // (precond = 1); D = wgt (npts real, pointwise) or 1 when wgt is null.
@@ -165,7 +175,9 @@ bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, d
 bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev);
 // one-sided Jacobi SVD: G (rows x m) -> G V = U diag(s); G overwritten by U diag(s) (columns),
 // V (m x m) receives V, s (m, device) the column norms; columns sorted by descending s.
-bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s);
+// conv: a sweep without rotations of cosine above conv ends the iteration
+bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s,
+                     double conv = 1e-13);
 
 // pivoted Cholesky of a Gram matrix A (m x m, destroyed; diagonally scaled inside):
 // R (m x m, ld m) gets r columns with R^H A R = I; *rank_dev = r (Schur diagonal cut rtol)

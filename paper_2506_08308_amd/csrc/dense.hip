@@ -410,7 +410,7 @@ __global__ void k_zero_int(int* p) { *p = 0; }
 template <int W>
 __global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double2* G, int ldg, double2* V, int ldv,
                                                          int nblk, int rnd, const double* __restrict__ frob2,
-                                                         int* rotations) {
+                                                         int* rotations, double conv) {
     constexpr int N2 = 2 * W, PA = N2 + 1;
     extern __shared__ double2 sm[];
     __shared__ double prm[W][4];
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double
     }
     __syncthreads();
     const double negl = 1e-30 * (*frob2);
-    const double tol = 1e-15, conv = 1e-13;
+    const double tol = 1e-15;
     const int tpp = nt / W;
     const int pair = t / tpp, sub = t % tpp;
     for (int r2 = 0; r2 < N2 - 1; ++r2) {
@@ -757,7 +757,7 @@ bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev)
     return hip_check(c, hipGetLastError(), "k_small_cholesky");
 }
 
-bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s) {
+bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s, double conv) {
     if (m <= 0) return BDG_OK;
     if (m > 512 || rows > 512) return ctx_fail(c, BDG_EINVAL, "small_svd: size out of range");
     // block width: both blocks of G (rows) and V (m) must fit in the workgroup's LDS
@@ -798,13 +798,13 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
         for (int rnd = 0; rnd < nblk - 1; ++rnd) {
             if (w == 16)
                 hipLaunchKernelGGL(k_bjacobi_round_g<16>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
-                                   ldv, nblk, rnd, (const double*)frob2, counter);
+                                   ldv, nblk, rnd, (const double*)frob2, counter, conv);
             else if (w == 8)
                 hipLaunchKernelGGL(k_bjacobi_round_g<8>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
-                                   ldv, nblk, rnd, (const double*)frob2, counter);
+                                   ldv, nblk, rnd, (const double*)frob2, counter, conv);
             else
                 hipLaunchKernelGGL(k_bjacobi_round_g<4>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
-                                   ldv, nblk, rnd, (const double*)frob2, counter);
+                                   ldv, nblk, rnd, (const double*)frob2, counter, conv);
         }
         BDG_HIP(c, hipGetLastError());
         int h = 0;

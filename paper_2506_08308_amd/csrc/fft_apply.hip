@@ -216,6 +216,8 @@ __global__ void __launch_bounds__(512) k_strided(FieldAddr<V> io, long long nfie
 // pointwise coupling with the input fields.  FULL: the lines are loaded from X and
 // transformed forward, multiplied and inverted here (1-D grids).
 // FORM 1 (f, g):  y_f = T g + H_- g,  y_g = T f + H_+ f   (transpose swaps H_+ and H_-)
+// FORM 2 / 3 (u, v), complex ground state (float64 only; 21 coefficient fields):
+//                 y_u = T u + A u + B v,  y_v = -+(T v + conj(B) u + conj(A) v)  (3: the K form)
 // FORM 0 (u, v):  y_u = T u + A u + B v,  y_v = -(T v + B u + A v)  with A = (H_+ + H_-)/2,
 //                 B = (H_+ - H_-)/2 (transpose flips the sign of the B terms)
 // ----------------------------------------------------------------------------------------
@@ -292,6 +294,43 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
             ta[cc] = lds[(cc * QL + qq) * N + e];
             tb[cc] = lds[((cc + 3) * QL + qq) * N + e];
         }
+        V ya[3], yb[3];
+        if constexpr (FORM >= 2) {
+            // complex ground state: A Hermitian (real diagonal, upper 01, 02, 12), B symmetric
+            R ad[3], ao[6], bb[12];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) ad[s] = coef[s * npts + p];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) ao[s] = coef[(3 + s) * npts + p];
+#pragma unroll
+            for (int s = 0; s < 12; ++s) bb[s] = coef[(9 + s) * npts + p];
+            auto aent = [&](int a, int c2) -> V {
+                if (a == c2) return cmk<V>(ad[a], 0);
+                const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
+                const int e = lo == 0 ? hi - 1 : 2;                 // 01 -> 0, 02 -> 1, 12 -> 2
+                const V up = cmk<V>(ao[2 * e], ao[2 * e + 1]);
+                return a < c2 ? up : cmk<V>(up.x, -up.y);
+            };
+            auto bent = [&](int a, int c2) -> V {
+                const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
+                const int e = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+                return cmk<V>(bb[2 * e], bb[2 * e + 1]);
+            };
+            const R sv = FORM == 2 ? (R)-1 : (R)1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                V su = ta[a], sw = tb[a];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    const V A_ = aent(a, cc), B_ = bent(a, cc);
+                    // u row: A u + B v;  v row: conj(B) u + conj(A) v
+                    su = cadd(su, cadd(cmul(A_, xa[cc]), cmul(B_, xb[cc])));
+                    sw = cadd(sw, cadd(cmul(cmk<V>(B_.x, -B_.y), xa[cc]), cmul(cmk<V>(A_.x, -A_.y), xb[cc])));
+                }
+                ya[a] = su;
+                yb[a] = cmk<V>(sv * sw.x, sv * sw.y);
+            }
+        } else {
         R P[6], M[6];
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
@@ -304,7 +343,6 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
             const int idx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
             return S[idx];
         };
-        V ya[3], yb[3];
         if (FORM == 1) {
             const R* Pa = TRANS ? M : P;   // operator acting on f (output half 1)
             const R* Pb = TRANS ? P : M;   // operator acting on g (output half 0)
@@ -335,6 +373,7 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
                 ya[a] = su;
                 yb[a] = cmk<V>(-sv.x, -sv.y);
             }
+        }
         }
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
@@ -422,7 +461,7 @@ bdg_status run_couple(bdg_ctx* c, FieldAddr<const V> xin, FieldAddr<V> yout, lon
         dim3 grid((unsigned)(nvec * ngroups));
         hipLaunchKernelGGL((k_couple<V, NN, FORM, TRANS, FULL>), grid, dim3(CoupleCfg<NN>::THREADS), 0,
                            c->stream, xin, yout, lpf, ngroups, (const V*)tw_of<R>(c, 0), ms, c->n[1],
-                           coef_of<R>(c));
+                           FORM >= 2 ? (const R*)c->ccoef : coef_of<R>(c));
     });
     return hip_check(c, hipGetLastError(), "k_couple");
 }
@@ -456,6 +495,14 @@ bdg_status launch_apply(bdg_ctx* c, int form, int transpose, int nvec,
         return transpose ? apply_impl<V, 1, 1>(c, nvec, xa, ya) : apply_impl<V, 1, 0>(c, nvec, xa, ya);
     }
     return transpose ? apply_impl<V, 0, 1>(c, nvec, xa, ya) : apply_impl<V, 0, 0>(c, nvec, xa, ya);
+}
+
+bdg_status launch_apply_complex(bdg_ctx* c, int kform, int nvec, BlockRef<const double2> X, BlockRef<double2> Y) {
+    if (nvec <= 0) return BDG_OK;
+    if (!c->complex_gs || !c->ccoef) return ctx_fail(c, BDG_ESTATE, "complex apply needs a complex ground state");
+    FieldAddr<const double2> xa = fa_block<const double2>(X.lo, X.hi, X.vstride, c->npts);
+    FieldAddr<double2> ya = fa_block<double2>(Y.lo, Y.hi, Y.vstride, c->npts);
+    return kform ? apply_impl<double2, 3, 0>(c, nvec, xa, ya) : apply_impl<double2, 2, 0>(c, nvec, xa, ya);
 }
 
 template <typename R>

@@ -284,6 +284,7 @@ extern "C" bdg_status bdg_ground_state(bdg_ctx* c, const double* phi0_dev, doubl
         return finish(hip_check(c, hipGetLastError(), "copy phi"));
     if (hipStreamSynchronize(c->stream) != hipSuccess) return finish(hip_check(c, hipGetLastError(), "sync"));
     c->has_gs = true;
+    c->complex_gs = false;
     if (st != BDG_OK) return finish(ctx_fail(c, BDG_ENOCONV, "ground state: iteration limit reached"));
     return finish(BDG_OK);
 }

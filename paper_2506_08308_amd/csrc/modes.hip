@@ -14,6 +14,7 @@ namespace {
 // cs[2 (l nt + s)] = cos(omega_l t_s), cs[2 (l nt + s) + 1] = sin(omega_l t_s)
 __global__ void __launch_bounds__(256) k_perturbed_density(long long npts, int nmodes, int nt,
                                                            const double* __restrict__ phi,
+                                                           const double2* __restrict__ phic,
                                                            const double2* __restrict__ uv,
                                                            const double* __restrict__ cs, double eps,
                                                            double* __restrict__ out) {
@@ -25,14 +26,15 @@ __global__ void __launch_bounds__(256) k_perturbed_density(long long npts, int n
         const int l = (int)(e / (3 * npts));
         const double2 u = uv[((long long)l * 6 + j) * npts + p];
         const double2 v = uv[((long long)l * 6 + 3 + j) * npts + p];
-        const double ph = phi[(long long)j * npts + p];
+        // real ground state (phi) or complex one (phic)
+        const double2 ph = phic ? phic[(long long)j * npts + p] : double2{phi[(long long)j * npts + p], 0.0};
         for (int s = 0; s < nt; ++s) {
             const double c = cs[2 * ((long long)l * nt + s)];
             const double sn = cs[2 * ((long long)l * nt + s) + 1];
             // u e^{-i w t} + conj(v) e^{i w t}
             const double re = (u.x + v.x) * c + (u.y + v.y) * sn;
             const double im = (u.y - v.y) * c + (v.x - u.x) * sn;
-            const double a = ph + eps * re, b = eps * im;
+            const double a = ph.x + eps * re, b = ph.y + eps * im;
             out[(((long long)l * nt + s) * 3 + j) * npts + p] = a * a + b * b;
         }
     }
@@ -64,7 +66,8 @@ extern "C" bdg_status bdg_perturbed_density(bdg_ctx* c, int nmodes, const double
     const long long total = (long long)nmodes * 3 * c->npts;
     const unsigned nblk = (unsigned)std::min<long long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_perturbed_density, dim3(nblk), dim3(256), 0, c->stream, c->npts, nmodes, nt,
-                       (const double*)c->phi, (const double2*)UV_dev, (const double*)dcs, eps, (double*)out_dev);
+                       (const double*)c->phi, c->complex_gs ? (const double2*)c->phic : nullptr,
+                       (const double2*)UV_dev, (const double*)dcs, eps, (double*)out_dev);
     BDG_HIP(c, hipGetLastError());
     // the host table must outlive the copy
     BDG_HIP(c, hipStreamSynchronize(c->stream));

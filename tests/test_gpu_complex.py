@@ -1,0 +1,111 @@
+"""Complex ground states (the general BdG form of Section 2.1) on the GPU: the (u, v) apply
+against the oracle's literal operator, the pencil eigensolver against the oracle's dense
+spectrum and the exact spectra of oracle.complexgs (rotation invariance, Doppler shift), the
+perturbed density with a complex Phi, and the argument rules."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bdg, complexgs, groundstate as gs, modes
+from tests.gpu_util import make_ctx, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+ROT = [
+    W.Workload("1d_64_fm", 1, (64,), (8.0,), "harmonic1", 10.0, -0.5, 0.2),
+    W.Workload("1d_64_afm", 1, (64,), (8.0,), "harmonic1", 10.0, 1.0, 0.3),
+    W.Workload("2d_16x32_fm", 2, (16, 32), (5.0, 6.0), "harmonic2_aniso", 20.0, -1.0, 0.1),
+]
+
+
+def _rotated(w):
+    V = W.potential(w)
+    r = gs.ground_state(V, w.beta_n, w.beta_s, w.mass, w.magnetization, w.n, w.L, W.initial_spinor(w), tol=1e-13)
+    return V, r, complexgs.rotate(r.phi, 0.7, 0.3)
+
+
+@pytest.mark.parametrize("w", ROT, ids=lambda w: w.name)
+def test_complex_apply_matches_oracle(w):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Form
+    say("complex apply", w.name)
+    V, r, phc = _rotated(w)
+    ctx = make_ctx(w, None, V)
+    ctx.set_ground_state_complex(torch.from_numpy(phc), r.mu)
+    X = W.random_block((3, 6) + w.shape, seed=5, smooth=0.0)
+    Y = ctx.apply(torch.from_numpy(X).to("cuda"), Form.UV).cpu().numpy()
+    ref = bdg.apply_uv(bdg.coefficients(phc, r.mu, V, w.beta_n, w.beta_s), X, w.n, w.L)
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    say(f"   max rel err {err:.2e}")
+    assert err <= 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("w", ROT, ids=lambda w: w.name)
+def test_rotated_state_spectrum_equals_the_real_one(w):
+    torch = torch_cuda()
+    say("complex eigs", w.name)
+    V, r, phc = _rotated(w)
+    k = 8
+    om_d, _ = bdg.positive_eigs_dense(bdg.dense_uv(bdg.coefficients(r.phi, r.mu, V, w.beta_n, w.beta_s), w.n, w.L), k)
+    ctx = make_ctx(w, None, V)
+    ctx.set_ground_state_complex(torch.from_numpy(phc), r.mu)
+    out = ctx.eigs(k, 12, tol=1e-8, max_iter=2000, seed=3)
+    say(f"   {out['iters']} iterations, max rel err {np.max(np.abs(np.array(out['omega']) - om_d) / om_d):.2e}")
+    assert np.allclose(out["omega"], om_d, rtol=1e-9)
+    # eigenvectors: the oracle's complex operator and the normalization int |u|^2 - |v|^2 = 1
+    uv = out["uv"].cpu().numpy()
+    coef = bdg.coefficients(phc, r.mu, V, w.beta_n, w.beta_s)
+    Y = bdg.apply_uv(coef, uv, w.n, w.L)
+    R = Y - np.array(out["omega"]).reshape((k,) + (1,) * (uv.ndim - 1)) * uv
+    rel = np.linalg.norm(R.reshape(k, -1), axis=1) / np.linalg.norm(uv.reshape(k, -1), axis=1)
+    assert rel.max() <= 1e-7
+    hd = np.prod(w.h)
+    nrm = hd * (np.sum(np.abs(uv[:, :3]) ** 2, axis=tuple(range(1, uv.ndim))) -
+                np.sum(np.abs(uv[:, 3:]) ** 2, axis=tuple(range(1, uv.ndim))))
+    assert np.allclose(nrm, 1.0, atol=1e-10)
+    ctx.close()
+
+
+def test_moving_state_spectrum_is_doppler_shifted():
+    torch = torch_cuda()
+    n, L, bn, bs = (16, 8), (4.0, 3.0), 100.0, 40.0
+    w = W.Workload("2d_moving_polar", 2, n, L, "zero", bn, bs, 0.0)
+    say("complex eigs", w.name)
+    phi, mu, q = complexgs.moving_polar_state(n, L, bn, 1)
+    ref = complexgs.moving_polar_spectrum(n, L, bn, bs, q, 12)
+    ctx = make_ctx(w, None, np.zeros(tuple(reversed(n))))
+    ctx.set_ground_state_complex(torch.from_numpy(phi), mu)
+    out = ctx.eigs(12, 16, tol=1e-8, max_iter=2000, seed=4)
+    say(f"   {out['iters']} iterations, omega {np.round(out['omega'], 6)}")
+    assert np.allclose(out["omega"], ref, rtol=1e-9, atol=1e-10)
+    ctx.close()
+
+
+def test_complex_perturbed_density_and_argument_rules():
+    torch = torch_cuda()
+    from paper_2506_08308_amd import BdgError, Form, Precision, _lib
+    w = ROT[0]
+    V, r, phc = _rotated(w)
+    ctx = make_ctx(w, None, V)
+    ctx.set_ground_state_complex(torch.from_numpy(phc), r.mu)
+    out = ctx.eigs(4, 8, tol=1e-8, seed=1)
+    n = ctx.perturbed_density(out["omega"], out["uv"], 0.1, [0.0, 2.0]).cpu().numpy()
+    ref = modes.perturbed_density(phc, out["uv"].cpu().numpy(), out["omega"], 0.1, [0.0, 2.0])
+    assert np.abs(n - ref).max() <= 1e-13 * np.abs(ref).max()
+    X = torch.zeros((1, 6) + w.shape, dtype=torch.complex128, device="cuda")
+    with pytest.raises(BdgError) as e:
+        ctx.apply(X, Form.FG)
+    assert e.value.status == _lib.BDG_EINVAL
+    with pytest.raises(BdgError) as e:
+        ctx.eigs_grad(out["omega"], out["uv"])
+    assert e.value.status == _lib.BDG_EINVAL
+    # a real ground state returns the context to the real path
+    ctx.set_ground_state(torch.from_numpy(r.phi), r.mu)
+    assert ctx.apply(X, Form.FG).shape == X.shape
+    ctx.close()
+    c32 = make_ctx(w, Precision.FP32_APPLY, V)
+    with pytest.raises(BdgError) as e:
+        c32.set_ground_state_complex(torch.from_numpy(phc), r.mu)
+    assert e.value.status == _lib.BDG_EINVAL
+    c32.close()
