@@ -20,9 +20,14 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 }
 
 // ----------------------------------------------------------------------------------------
-// Gram: part[s] = A^H B over the K-range of split s, tile 64 x 64 per workgroup (4 waves of
-// 32 x 32).  The real form uses the interleaved doubles as 2K real rows:
-//   Re C = a^T b,  Im C = a^T b'  with b'[2k] = Im B[k], b'[2k+1] = -Re B[k].
+// Gram: part[s] = A^H B over the K-range of split s.  Two tilings, picked per launch by a
+// cost model measured on the device:
+//  * k_gram: tiles of 64 x 64, 4 waves of 32 x 32.  The real form uses the interleaved
+//    doubles as 2K real rows: Re C = a^T b,  Im C = a^T b'  with b'[2k] = Im B[k],
+//    b'[2k+1] = -Re B[k].  Each wave reuses every fragment in two or four MFMAs.
+//  * k_gram80: tiles of 80 x 80 (5 x 5 blocks of 16), 10 waves; no padding for m1, m2 that
+//    are multiples of 80 (the solver's blocks), where the 64-tiling pads 80 to 128.
+//  * k_gram_thin: m1 <= 16, one block row.
 // ----------------------------------------------------------------------------------------
 struct SegList {
     const double2* p[4];
@@ -34,6 +39,21 @@ __device__ __forceinline__ const double2* seg_col(const SegList& sl, int col, lo
     int sg = 0;
     while (sg + 1 < sl.nseg && col >= sl.start[sg + 1]) ++sg;
     return sl.p[sg] + (long long)(col - sl.start[sg]) * ld;
+}
+
+// The same with the segment picked by selects over the (uniform) segment table: a per-lane
+// index into the argument block compiles to vector loads, and waiting on them also waits on
+// the prefetch loads already in flight.
+__device__ __forceinline__ const double2* seg_col_sel(const SegList& sl, int col, long long ld) {
+    const double2* p = sl.p[0];
+    int s0 = 0;
+#pragma unroll
+    for (int g = 1; g < 4; ++g)
+        if (g < sl.nseg && col >= sl.start[g]) {
+            p = sl.p[g];
+            s0 = sl.start[g];
+        }
+    return p + (long long)(col - s0) * ld;
 }
 
 constexpr int GT = 64;          // output tile edge
@@ -172,15 +192,224 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
             }
 }
 
+// Tiles of Q x Q blocks of 16 x 16 (k_gram80: Q = 5) on 2 Q waves.  Wave w computes the real
+// (w even) or imaginary (w odd) part of its blocks with one A fragment per block row:
+//   Re C = a^T b,  Im C = a'^T b  with a'[2k] = -Im A[k], a'[2k+1] = Re A[k],
+// so it holds one accumulator per block.  Off-diagonal tiles give the pair w / 2 block row
+// w / 2, all Q blocks.  A diagonal tile of a Hermitian Gram computes its Q (Q + 1) / 2 upper
+// blocks only, numbered row by row and dealt out ND to a pair ((Q + 1) / 2 each for odd Q).
+template <int Q>
+struct GramShape {
+    static constexpr int T = 16 * Q;
+    static constexpr int NT = 128 * Q;
+    static constexpr int NUP = Q * (Q + 1) / 2;
+    static constexpr int ND = (NUP + Q - 1) / Q;
+};
+
+// One tile over the rows [k0, k1).
+template <int Q, int NB, bool TRI>
+__device__ __forceinline__ void gram_tile(double* la, double* lb, bool one_panel, long long k0, long long k1,
+                                          int p0, int q0, int m1, int m2, const SegList& A, long long lda,
+                                          const SegList& B, long long ldb, double2* __restrict__ out) {
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int pair = wave >> 1, part = wave & 1;
+    int bi[NB], bj[NB];
+    bool live[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        if (TRI) {
+            int e = pair * NB + k;
+            live[k] = e < GramShape<Q>::NUP;
+            if (!live[k]) e = 0;
+            int r = 0;
+            while (e >= Q - r) {
+                e -= Q - r;
+                ++r;
+            }
+            bi[k] = r;
+            bj[k] = r + e;
+        } else {
+            live[k] = true;
+            bi[k] = pair;
+            bj[k] = k;
+        }
+    }
+    const double* lbr = one_panel ? la : lb;
+    d4 acc[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc[k] = d4{0, 0, 0, 0};
+    // loader mapping: 16 lanes per column chunk, 8 Q columns per pass, 2 passes
+    const int lk = t & 15, lc = t >> 4;
+    // the next chunk is held in registers while the current one is multiplied
+    double2 ra[2], rb[2];
+    auto gload = [&](long long kc) {
+        const long long kk = kc + lk;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int col = lc + 8 * Q * pass;
+            ra[pass] = (kk < k1 && p0 + col < m1) ? seg_col_sel(A, p0 + col, lda)[kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && !one_panel && q0 + col < m2) ? seg_col_sel(B, q0 + col, ldb)[kk]
+                                                                 : double2{0, 0};
+        }
+    };
+    // real rows ks + lane / 16 with ks a multiple of 4: the parity is fixed per lane.  The
+    // real part takes a = A[kr]; the imaginary part a' = (-Im, Re) of the complex pair:
+    //   Re C = a^T b,  Im C = a'^T b.
+    const bool odd = (lane >> 4) & 1;
+    const bool hi = odd != (part == 1);          // take the second double of the pair
+    const bool neg = part == 1 && !odd;
+    gload(k0);
+    for (long long kc = k0; kc < k1; kc += GKC) {
+        __syncthreads();
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int col = lc + 8 * Q * pass;
+            *reinterpret_cast<double2*>(&la[col * GPAD + 2 * lk]) = ra[pass];
+            if (!one_panel) *reinterpret_cast<double2*>(&lb[col * GPAD + 2 * lk]) = rb[pass];
+        }
+        __syncthreads();
+        if (kc + GKC < k1) gload(kc + GKC);
+#pragma unroll
+        for (int ks = 0; ks < GKR; ks += 4) {
+            const int kr = ks + (lane >> 4);        // real row of this lane
+            const int kp = ks + ((lane >> 4) & 2);  // its complex pair (ks is a multiple of 4)
+            const int ci = lane & 15;
+            auto frag = [&](int blk) {
+                const double2 pa = *reinterpret_cast<const double2*>(&la[(16 * blk + ci) * GPAD + kp]);
+                const double v = hi ? pa.y : pa.x;
+                return neg ? -v : v;
+            };
+            const double a0 = TRI ? 0.0 : frag(pair);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const double a = TRI ? frag(bi[k]) : a0;
+                acc[k] = mfma(a, lbr[(16 * bj[k] + ci) * GPAD + kr], acc[k]);
+            }
+        }
+    }
+    // write the partial blocks: register r of lane l holds D[4 r + l / 16][l % 16]
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        if (!live[k]) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = p0 + 16 * bi[k] + 4 * r + (lane >> 4);
+            const int q = q0 + 16 * bj[k] + (lane & 15);
+            if (p < m1 && q < m2) reinterpret_cast<double*>(&out[(long long)q * m1 + p])[part] = acc[k][r];
+        }
+    }
+}
+
+// Four waves per SIMD (<= 128 registers): one workgroup of 10 waves per CU
+__global__ void __launch_bounds__(640) __attribute__((amdgpu_waves_per_eu(4)))
+k_gram80(long long K, int m1, int m2, SegList A, long long lda, SegList B, long long ldb, long long kper, int tn,
+         int herm, int same, int ntiles, long long total, long long per_xcd, double2* __restrict__ part) {
+    constexpr int Q = 5;
+    constexpr int T = GramShape<Q>::T;
+    __shared__ __align__(16) double la[T * GPAD];
+    __shared__ __align__(16) double lb[T * GPAD];
+    long long split;
+    int ti, tj;
+    if (!gram_item(blockIdx.x, per_xcd, total, ntiles, tn, herm, &split, &ti, &tj)) return;
+    double2* out = part + split * m1 * m2;
+    const long long k0 = split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    // a diagonal tile of a Gram of one block with itself (A == B) reads one panel; a diagonal
+    // tile of a Hermitian Gram computes its upper blocks only (the reduction mirrors the rest)
+    const bool one_panel = same && ti == tj;
+    if (herm && ti == tj)
+        gram_tile<Q, GramShape<Q>::ND, true>(la, lb, one_panel, k0, k1, ti * T, tj * T, m1, m2, A, lda, B, ldb,
+                                             out);
+    else
+        gram_tile<Q, Q, false>(la, lb, one_panel, k0, k1, ti * T, tj * T, m1, m2, A, lda, B, ldb, out);
+}
+
+// Thin Gram (m1 <= 16, e.g. projections onto a few deflation vectors and single dot
+// products): one 16-row block of C.  A workgroup of 4 waves covers 64 columns of B over one
+// K-split, wave w the block column w, with the real and imaginary parts from a and a' as in
+// k_gram80.  Waves whose columns lie beyond m2 only help stage the panels.  The 64-tiling
+// would execute at least four times the matrix-core work here.
+__global__ void __launch_bounds__(256) k_gram_thin(long long K, int m1, int m2, SegList A, long long lda,
+                                                   SegList B, long long ldb, long long kper, int ncg,
+                                                   long long total, long long per_xcd,
+                                                   double2* __restrict__ part) {
+    __shared__ __align__(16) double la[16 * GPAD];
+    __shared__ __align__(16) double lb[64 * GPAD];
+    const long long L = blockIdx.x;
+    const long long w = (L & 7) * per_xcd + (L >> 3);
+    if (w >= total) return;
+    const long long split = w / ncg;
+    const int q0 = (int)(w % ncg) * 64;
+    double2* out = part + split * m1 * m2;
+    const long long k0 = split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool idle = q0 + 16 * wave >= m2;
+    // loader: 16 lanes per column chunk; A: 16 columns, B: 4 passes of 16 columns
+    const int lk = t & 15, lc = t >> 4;
+    double2 ra, rb[4];
+    auto gload = [&](long long kc) {
+        const long long kk = kc + lk;
+        ra = (kk < k1 && lc < m1) ? seg_col_sel(A, lc, lda)[kk] : double2{0, 0};
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const int col = q0 + lc + 16 * pass;
+            rb[pass] = (kk < k1 && col < m2) ? seg_col_sel(B, col, ldb)[kk] : double2{0, 0};
+        }
+    };
+    const bool odd = (lane >> 4) & 1;
+    d4 accr = d4{0, 0, 0, 0}, acci = d4{0, 0, 0, 0};
+    gload(k0);
+    for (long long kc = k0; kc < k1; kc += GKC) {
+        __syncthreads();
+        *reinterpret_cast<double2*>(&la[lc * GPAD + 2 * lk]) = ra;
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass)
+            *reinterpret_cast<double2*>(&lb[(lc + 16 * pass) * GPAD + 2 * lk]) = rb[pass];
+        __syncthreads();
+        if (kc + GKC < k1) gload(kc + GKC);
+        if (idle) continue;
+#pragma unroll
+        for (int ks = 0; ks < GKR; ks += 4) {
+            const int kr = ks + (lane >> 4);
+            const int kp = ks + ((lane >> 4) & 2);
+            const int ci = lane & 15;
+            const double2 pa = *reinterpret_cast<const double2*>(&la[ci * GPAD + kp]);
+            // a = A[kr]; a' = (-Im, Re) of the complex pair
+            const double a = odd ? pa.y : pa.x;
+            const double ap = odd ? pa.x : -pa.y;
+            const double b = lb[(16 * wave + ci) * GPAD + kr];
+            accr = mfma(a, b, accr);
+            acci = mfma(ap, b, acci);
+        }
+    }
+    if (idle) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = 4 * r + (lane >> 4);
+        const int q = q0 + 16 * wave + (lane & 15);
+        if (p < m1 && q < m2) {
+            double2 v;
+            v.x = accr[r];
+            v.y = acci[r];
+            out[(long long)q * m1 + p] = v;
+        }
+    }
+}
+
 // C = alpha * sum_s part[s] (fixed order); Hermitian: fill the lower triangle from the upper.
 __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restrict__ part, double alpha,
                               double2* __restrict__ C, int ldc, int herm) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)m1 * m2) return;
     int p = (int)(idx % m1), q = (int)(idx / m1);
-    // Hermitian: computed blocks are the upper tiles and, inside diagonal tiles, the upper
-    // 32 x 32 sub-tiles; everything below is mirrored
-    const bool mirror = herm && (p / 32) > (q / 32);
+    // Hermitian: both tilings compute every 16 x 16 block on and above the diagonal (k_gram
+    // also the 32 x 32 diagonal sub-tiles whole); everything below is mirrored
+    const bool mirror = herm && (p / 16) > (q / 16);
     const int ps = mirror ? q : p, qs = mirror ? p : q;
     double sx = 0, sy = 0;
     for (int s = 0; s < nsplit; ++s) {
@@ -680,8 +909,38 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
     if (!make_seglist(sa, na, &A, &m1) || !make_seglist(sb, nbs, &B, &m2))
         return ctx_fail(c, BDG_EINVAL, "gram: 1..4 segments");
     if (m1 <= 0 || m2 <= 0) return BDG_OK;
-    const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
-    if (hermitian && tm != tn) return ctx_fail(c, BDG_EINVAL, "gram: Hermitian form needs m1 == m2");
+    if (hermitian && m1 != m2) return ctx_fail(c, BDG_EINVAL, "gram: Hermitian form needs m1 == m2");
+    // Tiling by measured cost (MI355X, 6.3 M rows): a 64-tile takes 0.204 ms per 16 x 16 block
+    // it executes, an 80-tile 0.264 ms (the Hermitian diagonal tiles of either about as long
+    // as a full tile), so 80-tiles win where they remove padding: m = 80 against 128, 80 x 240
+    // against 128 x 256.
+    auto tiles = [&](int edge) -> long long {
+        const long long a = (m1 + edge - 1) / edge, b = (m2 + edge - 1) / edge;
+        return hermitian ? b * (b + 1) / 2 : a * b;
+    };
+    if (m1 <= 16) {
+        // thin form: every entry is computed, so the Hermitian flag only asks for the mirror
+        // (no entry of a 16 x 16 block lies below its diagonal block)
+        const int ncg = (m2 + 63) / 64;
+        long long nsplit = std::max<long long>(1, std::min<long long>((K + 511) / 512, 2048 / ncg));
+        long long kper = (K + nsplit - 1) / nsplit;
+        kper = ((kper + GKC - 1) / GKC) * GKC;
+        nsplit = (K + kper - 1) / kper;
+        void* ws = nullptr;
+        BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
+        const long long total = nsplit * ncg;
+        const long long per_xcd = (total + 7) / 8;
+        hipLaunchKernelGGL(k_gram_thin, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda,
+                           B, ldb, kper, ncg, total, per_xcd, (double2*)ws);
+        BDG_HIP(c, hipGetLastError());
+        const long long tot = (long long)m1 * m2;
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,
+                           (int)nsplit, (const double2*)ws, alpha, C, ldc, hermitian ? 1 : 0);
+        return hip_check(c, hipGetLastError(), "k_gram_thin");
+    }
+    const bool t80 = 25 * 264 * tiles(80) < 16 * 204 * tiles(64);
+    const int edge = t80 ? 80 : GT;
+    const int tm = (m1 + edge - 1) / edge, tn = (m2 + edge - 1) / edge;
     const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
     long long nsplit = std::max<long long>(1, std::min<long long>((K + 511) / 512, 2048 / ntiles));
     long long kper = (K + nsplit - 1) / nsplit;
@@ -695,12 +954,17 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
     for (int i = 0; same && i < na; ++i) same = sa[i].p == sb[i].p && sa[i].ncols == sb[i].ncols;
     const long long total = nsplit * ntiles;
     const long long per_xcd = (total + 7) / 8;
-    hipLaunchKernelGGL(k_gram, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda, B, ldb,
-                       kper, tn, hermitian ? 1 : 0, same ? 1 : 0, ntiles, total, per_xcd, (double2*)ws);
+    const int h = hermitian ? 1 : 0, sm = same ? 1 : 0;
+    if (t80)
+        hipLaunchKernelGGL(k_gram80, dim3((unsigned)(8 * per_xcd)), dim3(640), 0, c->stream, K, m1, m2, A, lda, B,
+                           ldb, kper, tn, h, sm, ntiles, total, per_xcd, (double2*)ws);
+    else
+        hipLaunchKernelGGL(k_gram, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda, B,
+                           ldb, kper, tn, h, sm, ntiles, total, per_xcd, (double2*)ws);
     BDG_HIP(c, hipGetLastError());
     const long long tot = (long long)m1 * m2;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,
-                       (int)nsplit, (const double2*)ws, alpha, C, ldc, hermitian ? 1 : 0);
+                       (int)nsplit, (const double2*)ws, alpha, C, ldc, h);
     return hip_check(c, hipGetLastError(), "k_gram");
 }
 

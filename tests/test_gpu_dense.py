@@ -22,10 +22,16 @@ def _p(t):
 
 
 # herm: 0 general A^H B; 1 Hermitian with B = A; 2 Hermitian with a distinct operand
-# B = D A (D real diagonal), the case of the Rayleigh-Ritz Grams S^H (H S)
+# B = D A (D real diagonal), the case of the Rayleigh-Ritz Grams S^H (H S).  The shapes reach
+# the three forms (64-tiles; 80-tiles for 70..80 columns and 80 x 240; the thin form for
+# m1 <= 16, single dot products included), diagonal and off-diagonal tiles, one and several
+# K-splits, and ragged row and column tails.
 @pytest.mark.parametrize("K,m1,m2,herm", [(37, 5, 7, 0), (1000, 40, 40, 0), (3072, 64, 64, 1), (5000, 80, 120, 0),
                                           (100000, 240, 240, 1), (70001, 16, 3, 0), (12, 130, 130, 1),
-                                          (20000, 144, 144, 2), (4099, 70, 70, 2)])
+                                          (20000, 144, 144, 2), (4099, 70, 70, 2), (50000, 160, 160, 1),
+                                          (20000, 80, 80, 1), (7001, 80, 80, 0), (30000, 80, 240, 0),
+                                          (100003, 75, 75, 2), (1000003, 1, 1, 0), (200000, 8, 80, 0),
+                                          (9000, 12, 12, 1)])
 def test_gram_matches_numpy(K, m1, m2, herm):
     torch = torch_cuda()
     from paper_2506_08308_amd import _lib
