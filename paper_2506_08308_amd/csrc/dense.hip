@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
             const int idx = u * 256 + t;
             const int l = l0 + idx / RW, row = idx % RW;
             rs[u] = double2{0, 0};
-            if (l < m && R0 + row < K) rs[u] = seg_col(segs, l, lds)[R0 + row];
+            if (l < m && R0 + row < K) rs[u] = seg_col_sel(segs, l, lds)[R0 + row];
         }
 #pragma unroll
         for (int u = 0; u < CPASS; ++u) {
@@ -492,17 +492,25 @@ __global__ void __launch_bounds__(256) k_update(long long K, SegList segs, long 
             double2 sv[RA];
 #pragma unroll
             for (int a = 0; a < RA; ++a) sv[a] = lsS[l * SP + wr + 16 * a + ri];
+            double2 cv[CB];
 #pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                const double2 cv = lsC[l * NC + 16 * b + ri];
+            for (int b = 0; b < CB; ++b) cv[b] = lsC[l * NC + 16 * b + ri];
+            // the four real products in rounds over all tiles, so that two MFMAs into one
+            // accumulator are 2 RA CB MFMAs apart
 #pragma unroll
-                for (int a = 0; a < RA; ++a) {
-                    accr[a][b] = mfma(sv[a].x, cv.x, accr[a][b]);
-                    accr[a][b] = mfma(-sv[a].y, cv.y, accr[a][b]);
-                    acci[a][b] = mfma(sv[a].x, cv.y, acci[a][b]);
-                    acci[a][b] = mfma(sv[a].y, cv.x, acci[a][b]);
+            for (int a = 0; a < RA; ++a)
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[a][b] = mfma(sv[a].x, cv[b].x, accr[a][b]);
+                    acci[a][b] = mfma(sv[a].x, cv[b].y, acci[a][b]);
                 }
-            }
+#pragma unroll
+            for (int a = 0; a < RA; ++a)
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[a][b] = mfma(-sv[a].y, cv[b].y, accr[a][b]);
+                    acci[a][b] = mfma(sv[a].y, cv[b].x, acci[a][b]);
+                }
         }
     }
 #pragma unroll
