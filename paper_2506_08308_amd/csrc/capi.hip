@@ -235,6 +235,7 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     c->prob = *pr;
     c->stream = (hipStream_t)hip_stream;
     c->device = dev;
+    c->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->dim = pr->dim;
     c->npts = 1;
     c->hd = 1.0;

@@ -42,6 +42,7 @@ struct bdg_ctx {
     bdg_problem prob{};
     hipStream_t stream = nullptr;
     int device = 0;
+    int ncu = 256;                // compute units of the device
     int dim = 1;
     int n[3] = {1, 1, 1};
     double L[3] = {1, 1, 1};

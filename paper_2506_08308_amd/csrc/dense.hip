@@ -910,6 +910,18 @@ static bool make_seglist(const Seg* segs, int nseg, SegList* sl, int* m) {
     return true;
 }
 
+// K-splits of a Gram launch: about 2048 workgroups, rounded to whole rounds of the
+// workgroups resident on the device at once (slots), so that the last round is not left
+// partly empty; at least 512 rows per split.  Returns the rows per split (a multiple of GKC).
+static long long gram_rows_per_split(long long K, long long items, long long slots, long long* nsplit) {
+    const long long rounds = std::max<long long>(1, (2048 + slots / 2) / slots);
+    long long ns = std::max<long long>(1, std::min<long long>((K + 511) / 512, rounds * slots / items));
+    long long kper = (K + ns - 1) / ns;
+    kper = ((kper + GKC - 1) / GKC) * GKC;
+    *nsplit = std::max<long long>(1, (K + kper - 1) / kper);
+    return kper;
+}
+
 bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long lda, const Seg* sb, int nbs,
                     long long ldb, double alpha, double2* C, int ldc, int hermitian) {
     SegList A, B;
@@ -930,10 +942,9 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         // thin form: every entry is computed, so the Hermitian flag only asks for the mirror
         // (no entry of a 16 x 16 block lies below its diagonal block)
         const int ncg = (m2 + 63) / 64;
-        long long nsplit = std::max<long long>(1, std::min<long long>((K + 511) / 512, 2048 / ncg));
-        long long kper = (K + nsplit - 1) / nsplit;
-        kper = ((kper + GKC - 1) / GKC) * GKC;
-        nsplit = (K + kper - 1) / kper;
+        long long nsplit = 1;
+        // five resident workgroups per CU (five waves per SIMD)
+        const long long kper = gram_rows_per_split(K, ncg, 5LL * c->ncu, &nsplit);
         void* ws = nullptr;
         BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
         const long long total = nsplit * ncg;
@@ -950,11 +961,9 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
     const int edge = t80 ? 80 : GT;
     const int tm = (m1 + edge - 1) / edge, tn = (m2 + edge - 1) / edge;
     const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
-    long long nsplit = std::max<long long>(1, std::min<long long>((K + 511) / 512, 2048 / ntiles));
-    long long kper = (K + nsplit - 1) / nsplit;
-    kper = ((kper + GKC - 1) / GKC) * GKC;
-    nsplit = (K + kper - 1) / kper;
-    if (nsplit < 1) nsplit = 1;
+    long long nsplit = 1;
+    // resident workgroups per CU: k_gram three (three waves per SIMD), k_gram80 one
+    const long long kper = gram_rows_per_split(K, ntiles, (t80 ? 1LL : 3LL) * c->ncu, &nsplit);
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
     // A == B (same segments, same stride): the diagonal tiles need one panel
