@@ -388,7 +388,7 @@ def campaign_modes(n=256, k=56, block=64, eps=0.1, t_snap=10.6):
               flush=True)
 
 
-def campaign_complex(n=256, L=12.0, beta_n=200.0, beta_s=80.0, k=32, block=48, tol=1e-8):
+def campaign_complex(n=256, L=12.0, beta_n=200.0, beta_s=80.0, k=32, block=48, tol=1e-10):
     """A complex ground state (Section 2.1, general BdG form): the uniform polar state moving with
     one grid quantum of momentum along x on [-L, L]^2.  Its spectrum is the Doppler-shifted
     Bogoliubov branches (computed here in closed form from the dispersion relation, no oracle).

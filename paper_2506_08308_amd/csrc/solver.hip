@@ -1515,10 +1515,9 @@ bdg_status eigs_pencil_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter,
     auto col = [&](int a, int slot) { return arr[a] + (long long)slot * nb * nh2; };
     double* d_om = dvec;
     double* d_n = dvec + nb;         // 2 nb norms
-    // The single-basis pencil iteration levels off near a relative residual of 1e-9 (measured
-    // on rotated and moving states, 30-100 times the float64 floor eps ||H|| / |w|; the
-    // eigenvalues then agree with the dense solution to ~1e-13): after stall_limit iterations
-    // without halving the largest residual it stops with BDG_ENOCONV and the last iterate.
+    // Per-column target max(tol, floor_c eps ||H|| / |w|) as in the real path; after
+    // stall_limit iterations without halving the largest residual the iteration stops with
+    // BDG_ENOCONV and the last iterate.
     const double null_tol = 1e-6, rtol = 1e-12, floor_c = 100.0;
     const int stall_limit = 100;
     double best_r = 1e300;
@@ -1688,7 +1687,16 @@ bdg_status eigs_pencil_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter,
             BDG_TRY(update_add(c, nh2, &sx, 1, nh2, Cx, nb, nact, 1.0, Wx, nh2, Wx, nh2));
             BDG_TRY(update_add(c, nh2, &skx, 1, nh2, Cx, nb, nact, 1.0, Wk, nh2, Wk, nh2));
         }
-        // P of the active columns, with explicit images
+        // unit columns: the corrections shrink with the residual, and beside the Ritz columns
+        // (K norm about w) a column of K norm about res sqrt(w / shift) falls under the K
+        // Gram's relative cut of 1e-20 on the squared norms once res nears 1e-9
+        BDG_TRY(colnorm2(c, nh2, nact, Wx, nh2, w.dscale));
+        hipLaunchKernelGGL(k_cols_scale, grid_cols(nh2, nact), dim3(256), 0, c->stream, nh2, nact, Wx, nh2,
+                           (const double*)w.dscale, 1);
+        hipLaunchKernelGGL(k_cols_scale, grid_cols(nh2, nact), dim3(256), 0, c->stream, nh2, nact, Wk, nh2,
+                           (const double*)w.dscale, 1);
+        BDG_HIP(c, hipGetLastError());
+        // P of the active columns, unit columns, with explicit images
         int np = 0;
         if (slotP >= 0) {
             np = nact;
@@ -1698,6 +1706,10 @@ bdg_status eigs_pencil_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter,
                 BDG_HIP(c, hipGetLastError());
                 std::swap(slotP, slotFree);
             }
+            BDG_TRY(colnorm2(c, nh2, np, col(0, slotP), nh2, w.dscale));
+            hipLaunchKernelGGL(k_cols_scale, grid_cols(nh2, np), dim3(256), 0, c->stream, nh2, np, col(0, slotP), nh2,
+                               (const double*)w.dscale, 1);
+            BDG_HIP(c, hipGetLastError());
             BDG_TRY(applyK(c, np, col(0, slotP), nh2, col(1, slotP)));
         }
         const int ns = np ? 3 : 2;

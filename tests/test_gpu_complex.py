@@ -50,16 +50,16 @@ def test_rotated_state_spectrum_equals_the_real_one(w):
     om_d, _ = bdg.positive_eigs_dense(bdg.dense_uv(bdg.coefficients(r.phi, r.mu, V, w.beta_n, w.beta_s), w.n, w.L), k)
     ctx = make_ctx(w, None, V)
     ctx.set_ground_state_complex(torch.from_numpy(phc), r.mu)
-    out = ctx.eigs(k, 12, tol=1e-8, max_iter=2000, seed=3)
+    out = ctx.eigs(k, 12, tol=1e-10, max_iter=2000, seed=3)
     say(f"   {out['iters']} iterations, max rel err {np.max(np.abs(np.array(out['omega']) - om_d) / om_d):.2e}")
-    assert np.allclose(out["omega"], om_d, rtol=1e-9)
+    assert np.allclose(out["omega"], om_d, rtol=1e-11)
     # eigenvectors: the oracle's complex operator and the normalization int |u|^2 - |v|^2 = 1
     uv = out["uv"].cpu().numpy()
     coef = bdg.coefficients(phc, r.mu, V, w.beta_n, w.beta_s)
     Y = bdg.apply_uv(coef, uv, w.n, w.L)
     R = Y - np.array(out["omega"]).reshape((k,) + (1,) * (uv.ndim - 1)) * uv
     rel = np.linalg.norm(R.reshape(k, -1), axis=1) / np.linalg.norm(uv.reshape(k, -1), axis=1)
-    assert rel.max() <= 1e-7
+    assert rel.max() <= 1e-9
     hd = np.prod(w.h)
     nrm = hd * (np.sum(np.abs(uv[:, :3]) ** 2, axis=tuple(range(1, uv.ndim))) -
                 np.sum(np.abs(uv[:, 3:]) ** 2, axis=tuple(range(1, uv.ndim))))
@@ -76,9 +76,9 @@ def test_moving_state_spectrum_is_doppler_shifted():
     ref = complexgs.moving_polar_spectrum(n, L, bn, bs, q, 12)
     ctx = make_ctx(w, None, np.zeros(tuple(reversed(n))))
     ctx.set_ground_state_complex(torch.from_numpy(phi), mu)
-    out = ctx.eigs(12, 16, tol=1e-8, max_iter=2000, seed=4)
+    out = ctx.eigs(12, 16, tol=1e-10, max_iter=2000, seed=4)
     say(f"   {out['iters']} iterations, omega {np.round(out['omega'], 6)}")
-    assert np.allclose(out["omega"], ref, rtol=1e-9, atol=1e-10)
+    assert np.allclose(out["omega"], ref, rtol=1e-11, atol=1e-12)
     ctx.close()
 
 
