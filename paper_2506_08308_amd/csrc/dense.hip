@@ -35,16 +35,10 @@ struct SegList {
     int nseg;
 };
 
+// Column col of a segment list, the segment picked by selects over the (uniform) segment
+// table: a per-lane index into the argument block would compile to vector loads, and waiting
+// on them also waits on the prefetch loads already in flight.
 __device__ __forceinline__ const double2* seg_col(const SegList& sl, int col, long long ld) {
-    int sg = 0;
-    while (sg + 1 < sl.nseg && col >= sl.start[sg + 1]) ++sg;
-    return sl.p[sg] + (long long)(col - sl.start[sg]) * ld;
-}
-
-// The same with the segment picked by selects over the (uniform) segment table: a per-lane
-// index into the argument block compiles to vector loads, and waiting on them also waits on
-// the prefetch loads already in flight.
-__device__ __forceinline__ const double2* seg_col_sel(const SegList& sl, int col, long long ld) {
     const double2* p = sl.p[0];
     int s0 = 0;
 #pragma unroll
@@ -248,8 +242,8 @@ __device__ __forceinline__ void gram_tile(double* la, double* lb, bool one_panel
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             const int col = lc + 8 * Q * pass;
-            ra[pass] = (kk < k1 && p0 + col < m1) ? seg_col_sel(A, p0 + col, lda)[kk] : double2{0, 0};
-            rb[pass] = (kk < k1 && !one_panel && q0 + col < m2) ? seg_col_sel(B, q0 + col, ldb)[kk]
+            ra[pass] = (kk < k1 && p0 + col < m1) ? seg_col(A, p0 + col, lda)[kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && !one_panel && q0 + col < m2) ? seg_col(B, q0 + col, ldb)[kk]
                                                                  : double2{0, 0};
         }
     };
@@ -354,11 +348,11 @@ __global__ void __launch_bounds__(256) k_gram_thin(long long K, int m1, int m2, 
     double2 ra, rb[4];
     auto gload = [&](long long kc) {
         const long long kk = kc + lk;
-        ra = (kk < k1 && lc < m1) ? seg_col_sel(A, lc, lda)[kk] : double2{0, 0};
+        ra = (kk < k1 && lc < m1) ? seg_col(A, lc, lda)[kk] : double2{0, 0};
 #pragma unroll
         for (int pass = 0; pass < 4; ++pass) {
             const int col = q0 + lc + 16 * pass;
-            rb[pass] = (kk < k1 && col < m2) ? seg_col_sel(B, col, ldb)[kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && col < m2) ? seg_col(B, col, ldb)[kk] : double2{0, 0};
         }
     };
     const bool odd = (lane >> 4) & 1;
@@ -465,7 +459,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             const int idx = u * 256 + t;
             const int l = l0 + idx / RW, row = idx % RW;
             rs[u] = double2{0, 0};
-            if (l < m && R0 + row < K) rs[u] = seg_col_sel(segs, l, lds)[R0 + row];
+            if (l < m && R0 + row < K) rs[u] = seg_col(segs, l, lds)[R0 + row];
         }
 #pragma unroll
         for (int u = 0; u < CPASS; ++u) {
