@@ -406,8 +406,21 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
     const bool mirror = herm && (p / 16) > (q / 16);
     const int ps = mirror ? q : p, qs = mirror ? p : q;
     double sx = 0, sy = 0;
-    for (int s = 0; s < nsplit; ++s) {
-        double2 v = part[(long long)s * m1 * m2 + (long long)qs * m1 + ps];
+    const long long plane = (long long)m1 * m2, off = (long long)qs * m1 + ps;
+    // eight loads in flight, summed in split order (the same rounding as one at a time)
+    int s = 0;
+    for (; s + 8 <= nsplit; s += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(s + u) * plane + off];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sx += v[u].x;
+            sy += v[u].y;
+        }
+    }
+    for (; s < nsplit; ++s) {
+        const double2 v = part[s * plane + off];
         sx += v.x;
         sy += v.y;
     }
@@ -884,7 +897,17 @@ __global__ void k_colnorm2_final(int ncols, int nchunk, const double* __restrict
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= ncols) return;
     double a = 0;
-    for (int c = 0; c < nchunk; ++c) a += part[(long long)col * nchunk + c];
+    const double* pc = part + (long long)col * nchunk;
+    // eight loads in flight, summed in chunk order (the same rounding as one at a time)
+    int c = 0;
+    for (; c + 8 <= nchunk; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pc[c + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; c < nchunk; ++c) a += pc[c];
     out[col] = a;
 }
 

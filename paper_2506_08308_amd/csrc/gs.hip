@@ -35,7 +35,17 @@ __global__ void k_final_sum(int nq, int nblk, const double* __restrict__ part, d
     const int q = threadIdx.x;
     if (q >= nq) return;
     double a = 0;
-    for (int b = 0; b < nblk; ++b) a += part[q * nblk + b];
+    const double* pq = part + (long long)q * nblk;
+    // eight loads in flight, summed in block order (the same rounding as one at a time)
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pq[b + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; b < nblk; ++b) a += pq[b];
     out[q] = a * scale;
 }
 
