@@ -20,8 +20,8 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 }
 
 // ----------------------------------------------------------------------------------------
-// Gram: part[s] = A^H B over the K-range of split s.  Two tilings, picked per launch by a
-// cost model measured on the device:
+// Gram: part[s] = A^H B over the K-range of split s.  Three forms, picked per launch: the
+// thin one when m1 <= 16, else the cheaper tiling by a cost model measured on the device.
 //  * k_gram: tiles of 64 x 64, 4 waves of 32 x 32.  The real form uses the interleaved
 //    doubles as 2K real rows: Re C = a^T b,  Im C = a^T b'  with b'[2k] = Im B[k],
 //    b'[2k+1] = -Re B[k].  Each wave reuses every fragment in two or four MFMAs.
