@@ -174,6 +174,8 @@ bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, d
                       double2* C, int ldc);
 // in-place lower Cholesky (upper part zeroed); *info_dev = 0 ok, j+1 if the j-th pivot fails
 bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev);
+// two independent factorizations of one size in one launch (one workgroup each)
+bdg_status small_cholesky2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda, int* info0_dev, int* info1_dev);
 // one-sided Jacobi SVD: G (rows x m) -> G V = U diag(s); G overwritten by U diag(s) (columns),
 // V (m x m) receives V, s (m, device) the column norms; columns sorted by descending s.
 // conv: a sweep without rotations of cosine above conv ends the iteration
@@ -183,6 +185,9 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
 // pivoted Cholesky of a Gram matrix A (m x m, destroyed; diagonally scaled inside):
 // R (m x m, ld m) gets r columns with R^H A R = I; *rank_dev = r (Schur diagonal cut rtol)
 bdg_status small_pchol_orth(bdg_ctx* c, int m, double2* A, int lda, double rtol, double2* R, int* rank_dev);
+// two independent problems of one size in one launch (one workgroup each)
+bdg_status small_pchol_orth2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda, double rtol, double2* R0,
+                             double2* R1, int* rank0_dev, int* rank1_dev);
 // LU with complete pivoting of B (p x q, destroyed): Cf (q x r, ld q), Cg (p x r, ld p) with
 // Cg^H B Cf = I_r; *rank_dev = r (pivot cut tol)
 bdg_status small_plu_biorth(bdg_ctx* c, int p, int q, double2* B, int ldb, double tol, double2* Cf, double2* Cg,

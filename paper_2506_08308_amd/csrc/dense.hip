@@ -576,7 +576,11 @@ __global__ void k_small_gemm(int tA, int tB, int m, int n, int k, double2 alpha,
 }
 
 // Right-looking Cholesky A = L L^H in one workgroup; lower triangle kept, upper zeroed.
-__global__ void __launch_bounds__(1024) k_small_cholesky(int m, double2* A, int lda, int* info) {
+// Workgroup b factors problem b of the launch (two independent matrices of one size).
+__global__ void __launch_bounds__(1024) k_small_cholesky(int m, int lda, double2* A0, int* info0, double2* A1,
+                                                         int* info1) {
+    double2* A = blockIdx.x ? A1 : A0;
+    int* info = blockIdx.x ? info1 : info0;
     __shared__ double piv;
     __shared__ int bad;
     const int t = threadIdx.x, nt = blockDim.x;
@@ -1055,7 +1059,13 @@ bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, d
 
 bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev) {
     if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_cholesky: m > 512");
-    hipLaunchKernelGGL(k_small_cholesky, dim3(1), dim3(1024), 0, c->stream, m, A, lda, info_dev);
+    hipLaunchKernelGGL(k_small_cholesky, dim3(1), dim3(1024), 0, c->stream, m, lda, A, info_dev, A, info_dev);
+    return hip_check(c, hipGetLastError(), "k_small_cholesky");
+}
+
+bdg_status small_cholesky2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda, int* info0_dev, int* info1_dev) {
+    if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_cholesky: m > 512");
+    hipLaunchKernelGGL(k_small_cholesky, dim3(2), dim3(1024), 0, c->stream, m, lda, A0, info0_dev, A1, info1_dev);
     return hip_check(c, hipGetLastError(), "k_small_cholesky");
 }
 

@@ -81,9 +81,23 @@ __device__ void lower_inverse(int r, Acc L, bool unit, double2* T) {
 
 // Pivoted Cholesky of the diagonally scaled Gram matrix A (m x m, destroyed).  Stops when the
 // largest remaining diagonal (Schur complement) is <= rtol.  R (m x m, ld m) receives
-// D^-1/2 P [L11^-H; 0] in its first r columns; *rank = r.
-__global__ void __launch_bounds__(1024) k_pchol_orth(int m, double2* A, int lda, double rtol, double2* Lb,
-                                                     double2* T, double2* R, int* rank) {
+// D^-1/2 P [L11^-H; 0] in its first r columns; *rank = r.  Workgroup b solves problem b of
+// the launch (two independent problems of one size, such as the f- and g-bases, share it).
+struct PcholProb {
+    double2* A;
+    double2* Lb;     // m x m workspace
+    double2* T;      // m x m workspace
+    double2* R;
+    int* rank;
+};
+
+__global__ void __launch_bounds__(1024) k_pchol_orth(int m, int lda, double rtol, PcholProb p0, PcholProb p1) {
+    const PcholProb& pb = blockIdx.x ? p1 : p0;
+    double2* A = pb.A;
+    double2* Lb = pb.Lb;
+    double2* T = pb.T;
+    double2* R = pb.R;
+    int* rank = pb.rank;
     __shared__ int perm[512];
     __shared__ double d[512];
     __shared__ double dinv[512];
@@ -305,8 +319,21 @@ bdg_status small_pchol_orth(bdg_ctx* c, int m, double2* A, int lda, double rtol,
     if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_pchol_orth: m > 512");
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 4, 2 * (size_t)m * m * sizeof(double2), &ws));
-    hipLaunchKernelGGL(k_pchol_orth, dim3(1), dim3(1024), 0, c->stream, m, A, lda, rtol, (double2*)ws,
-                       (double2*)ws + (size_t)m * m, R, rank_dev);
+    const PcholProb p{A, (double2*)ws, (double2*)ws + (size_t)m * m, R, rank_dev};
+    hipLaunchKernelGGL(k_pchol_orth, dim3(1), dim3(1024), 0, c->stream, m, lda, rtol, p, p);
+    return hip_check(c, hipGetLastError(), "k_pchol_orth");
+}
+
+bdg_status small_pchol_orth2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda, double rtol, double2* R0,
+                             double2* R1, int* rank0_dev, int* rank1_dev) {
+    if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_pchol_orth: m > 512");
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 4, 4 * (size_t)m * m * sizeof(double2), &ws));
+    double2* w = (double2*)ws;
+    const size_t mm = (size_t)m * m;
+    const PcholProb p0{A0, w, w + mm, R0, rank0_dev};
+    const PcholProb p1{A1, w + 2 * mm, w + 3 * mm, R1, rank1_dev};
+    hipLaunchKernelGGL(k_pchol_orth, dim3(2), dim3(1024), 0, c->stream, m, lda, rtol, p0, p1);
     return hip_check(c, hipGetLastError(), "k_pchol_orth");
 }
 

@@ -355,9 +355,8 @@ bdg_status rr_once(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const
     double2* X2 = w.buf[13];
     // orthonormal bases of the two spaces (pivoted Cholesky of the scaled Gram matrices)
     BDG_TRY(small_copy(c, m, m, Gf, m, T, m));
-    BDG_TRY(small_pchol_orth(c, m, T, m, rtol, Rf, w.info + 2));
-    BDG_TRY(small_copy(c, m, m, Gg, m, T, m));
-    BDG_TRY(small_pchol_orth(c, m, T, m, rtol, Rg, w.info + 3));
+    BDG_TRY(small_copy(c, m, m, Gg, m, B, m));
+    BDG_TRY(small_pchol_orth2(c, m, T, B, m, rtol, Rf, Rg, w.info + 2, w.info + 3));
     int rk[2];
     BDG_TRY(d2h(c, rk, w.info + 2, 2 * sizeof(int)));
     const int rf = rk[0], rg = rk[1];
@@ -380,8 +379,7 @@ bdg_status rr_once(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const
     BDG_TRY(small_gemm(c, 1, 0, r, r, m, ONE, Cg, m, T, m, ZERO, X2, m));
     hipLaunchKernelGGL(k_small_herm, dim3((unsigned)((r + 127) / 128), (unsigned)r), dim3(128), 0, c->stream, r, X1, m);
     hipLaunchKernelGGL(k_small_herm, dim3((unsigned)((r + 127) / 128), (unsigned)r), dim3(128), 0, c->stream, r, X2, m);
-    BDG_TRY(small_cholesky(c, r, X1, m, w.info));
-    BDG_TRY(small_cholesky(c, r, X2, m, w.info + 1));
+    BDG_TRY(small_cholesky2(c, r, X1, X2, m, w.info, w.info + 1));
     // G = L_K^H L_M -> B ; SVD -> V3, s[3]
     BDG_TRY(small_gemm(c, 1, 0, r, r, r, ONE, X2, m, X1, m, ZERO, B, m));
     BDG_TRY(small_svd(c, r, r, B, m, V3, m, w.s[3]));
