@@ -9,6 +9,11 @@ Default workload: the 3-D trap, 128^3 grid on [-8, 8]^3, V = (x^2 + y^2 + 4 z^2)
 beta_n = 400, beta_s = -4, M = 0.1, k = 64, block 80, residual 1e-8, float32-apply mixed
 precision; the float64 solve of the same problem is timed beside it (--no-fp64 skips it).
 
+Wall-clock budget (--budget-s, default 480 s from process start): at most one warmup solve
+runs, and timed solves stop once another one would not leave room for the float64 solve,
+the roofline launches and the CPU baseline; "steps" reports the solves actually timed
+(config.steps_requested the number asked for).
+
 Prints ONE JSON line.  ``roofline`` is the Gram kernel (k_gram, the largest kernel-time
 share of the solve) against the FP64 matrix peak; ``roofline_apply`` is the BdG apply against
 the HBM peak.  Both are timed live with HIP events on the context stream at the solve's own
@@ -27,6 +32,7 @@ import time
 
 import numpy as np
 
+T_START = time.time()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -44,6 +50,7 @@ WORKLOADS = {
     "c2_polar": (W.C2_POLAR, None),
     "c1": (W.C1, None),
 }
+CPU_BASELINE_RESERVE_S = 90.0
 KERNEL_SOURCES = {"gram": "paper_2506_08308_amd/csrc/dense.hip", "apply": "paper_2506_08308_amd/csrc/fft_apply.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -149,50 +156,78 @@ def copy_reference(reps=3):
     return ms
 
 
-def cpu_baseline(w, gpu_iters, budget_s=20.0):
-    """The CPU oracle's subspace iteration (numpy FP64 on the host cores) on a bounded sample:
-    a few iterations of the same algorithm on the same problem at a grid the host holds
-    (each axis halved until 14 FP64 blocks fit in 4 GB), extrapolated to the GPU's iteration
-    count and by DOF log DOF to the full grid."""
-    from oracle import bdg, groundstate as gs, lrep
+def _cpu_model():
     try:
-        import threadpoolctl
-        blas_threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
-    except Exception:
-        blas_threads = os.cpu_count()
-    n_s = w.n[0]
-    while n_s > 8 and 14 * w.block * 6 * (n_s ** w.dim) * 16 > 4e9:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, gpu_iters, iters=2):
+    """The CPU oracle's subspace iteration (numpy/scipy FP64 on the host cores) on a bounded
+    sample of the same problem: `iters` iterations at the largest grid of at most 64 points
+    per axis whose basis fits in half the free host memory, same k, block and seed-0 start
+    block.  The oracle's ground-state flow runs a bounded 50 steps (the per-iteration cost
+    does not depend on how far it got) and the deflation set-up is left out (a few
+    projections per iteration).  Per-iteration time is split into the FFT operator applies
+    (timed around them) and the rest (Gram matrices, projected problem, updates); the FFT
+    share is scaled by DOF log DOF and the rest by DOF to the full grid, then multiplied
+    by the GPU's iteration count."""
+    import psutil
+    from oracle import bdg, groundstate as gs, lrep, spectral
+    n_s = min(w.n[0], 64)
+    # the oracle holds about 30 half-blocks of block x 3 npts complex128 at once
+    free = psutil.virtual_memory().available
+    while n_s > 8 and 30 * w.block * 3 * (n_s ** w.dim) * 16 > 0.5 * free:
         n_s //= 2
     ws = W.scaled(w, n_s) if n_s != w.n[0] else w
     V = W.potential(ws)
-    t0 = time.time()
     r = gs.ground_state(V, ws.beta_n, ws.beta_s, ws.mass, ws.magnetization, ws.n, ws.L, W.initial_spinor(ws),
-                        tol=1e-10, max_iter=5000)
+                        tol=1e-10, max_iter=50)
     coef = bdg.coefficients(r.phi, r.mu, V, ws.beta_n, ws.beta_s)
     sigma, D = lrep.preconditioner_parameters(V, r.mu)
     prob = lrep.LrepProblem(coef, ws.n, ws.L, D)
-    Nm, Qg = lrep.deflation_sets(prob, r.phi, cg_tol=1e-10, sigma=sigma)
+    fft_s = [0.0]
+
+    def timed(fn):
+        def run(*a, **kw):
+            t = time.time()
+            out = fn(*a, **kw)
+            fft_s[0] += time.time() - t
+            return out
+        return run
+
+    prob.hplus, prob.hminus, prob.precond = timed(prob.hplus), timed(prob.hminus), timed(prob.precond)
     X0 = W.start_block(ws)
-    per_it, iters = None, 0
-    for n_it in (2, 4, 8):
-        t1 = time.time()
-        lrep.lrep_eigs(prob, ws.k, X0, 1e-30, max_iter=n_it, Nm=Nm, Qg=Qg, sigma=sigma)
-        per_it = (time.time() - t1) / n_it
-        iters = n_it
-        if time.time() - t0 > budget_s / 2:
-            break
-    scale = 1.0
+    t0 = time.time()
+    lrep.lrep_eigs(prob, ws.k, X0, 1e-30, max_iter=iters, sigma=sigma)
+    wall = time.time() - t0
+    per_it, fft_it = wall / iters, fft_s[0] / iters
+    s_fft, s_dof = 1.0, 1.0
     if ws is not w:
         d_full, d_s = 6 * w.npts, 6 * ws.npts
-        scale = (d_full * np.log2(d_full)) / (d_s * np.log2(d_s))
-    return {"value": round(per_it * gpu_iters * scale, 1), "unit": "s", "cores": int(blas_threads), "kind": "oracle",
-            "sample": f"{iters} iterations of the oracle subspace iteration (numpy FP64; BLAS on {blas_threads} "
-                      f"threads, numpy FFT on one) at grid {list(ws.n)}, block {ws.block}: {per_it:.3f} s per "
-                      f"iteration, x {gpu_iters} GPU iterations"
-                      + (f", x {scale:.1f} (DOF log DOF from {list(ws.n)} to {list(w.n)})" if ws is not w else "")}
+        s_dof = d_full / d_s
+        s_fft = (d_full * np.log2(d_full)) / (d_s * np.log2(d_s))
+    full_it = fft_it * s_fft + (per_it - fft_it) * s_dof
+    cores = spectral.WORKERS
+    return {"value": round(full_it * gpu_iters, 1), "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{iters} iterations (the start-up projection counted in) of the oracle subspace iteration "
+                      f"(numpy/scipy FP64, FFT and BLAS on {cores} threads of {os.cpu_count()} cores, "
+                      f"{_cpu_model()}) at grid {list(ws.n)}, k {ws.k}, block {ws.block}: {per_it:.2f} s per "
+                      f"iteration, {fft_it:.2f} s of it in FFT applies; scaled to {list(w.n)} by DOF log DOF "
+                      f"(x{s_fft:.2f}) for the FFT part and DOF (x{s_dof:.1f}) for the rest = {full_it:.1f} s "
+                      f"per iteration, x {gpu_iters} GPU iterations"}
 
 
-def solve(w, X0, steps, warmup, max_iter):
+def solve(w, X0, steps, warmup, max_iter, deadline=None, reserve_s=0.0, reserve_fn=None):
+    """Ground state (untimed), `warmup` untimed solves, then up to `steps` timed solves; a
+    further timed solve starts only when it is expected to end `reserve_s` (or
+    reserve_fn(longest step so far)) before `deadline` (time.time() scale), so the run fits
+    the caller's wall-clock budget."""
     import torch
     ctx = _context(w)
     t = time.time()
@@ -205,6 +240,10 @@ def solve(w, X0, steps, warmup, max_iter):
         log(f"[{w.name}] warmup {i}: {out['iters']} iterations")
     times, out = [], None
     for i in range(steps):
+        res_s = reserve_fn(max(times)) if (times and reserve_fn is not None) else (reserve_s or 0.0)
+        if times and deadline is not None and time.time() + max(times) + res_s > deadline:
+            log(f"[{w.name}] wall-clock budget reached after {len(times)} timed solves of {steps}")
+            break
         torch.cuda.synchronize()
         t0 = time.time()
         out = ctx.eigs(w.k, w.block, tol=w.tol, max_iter=max_iter, X0=X0, want_vectors=False)
@@ -444,6 +483,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-clock budget of the whole run from process start: at most one warmup solve, and "
+                         "timed solves stop early (the JSON line reports how many ran) so the float64 solve, "
+                         "rooflines and CPU baseline still fit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 solve timed beside the mixed one")
     ap.add_argument("--kernels-only", action="store_true")
@@ -477,8 +520,20 @@ def main():
     if args.campaign == "complex":
         campaign_complex()
         return
+    deadline = T_START + args.budget_s
+    cpu_reserve = 0.0 if args.no_cpu_baseline else CPU_BASELINE_RESERVE_S
+    warmup = min(args.warmup, 1)
     X0 = torch.from_numpy(W.start_block(w)).to("cuda")
-    ctx, out, times, gs_s = solve(w, X0, args.steps, args.warmup, args.max_iter)
+
+    def reserve(step_s):
+        # what must still fit after the last timed solve: the float64 solve beside it, the
+        # roofline launches and the CPU baseline
+        return (1.2 * step_s + 10.0 if w64 is not None else 0.0) + 15.0 + cpu_reserve
+
+    # the reserve depends on the step time, known after the first solve; solve() checks
+    # before each further timed solve
+    ctx, out, times, gs_s = solve(w, X0, args.steps, warmup, args.max_iter, deadline=deadline,
+                                  reserve_fn=reserve)
     st = ctx.stats()
     ms = 1000.0 * float(np.mean(times))
     g_ms, g_flops = gram_launch(ctx, w)
@@ -501,21 +556,29 @@ def main():
               "phase_ms": {k: round(st[k], 1) for k in ("apply_ms", "precond_ms", "gram_ms", "small_ms",
                                                        "update_ms", "setup_ms")},
               "ground_state_s": round(gs_s, 3), "omega_first": [round(v, 12) for v in out["omega"][:4]],
-              "max_residual": max(out["residual"])}
+              "max_residual": max(out["residual"]), "step_times_s": [round(t, 3) for t in times],
+              "steps_requested": args.steps, "warmup_requested": args.warmup,
+              "budget_s": args.budget_s}
     if w64 is not None:
-        ctx64, out64, t64, _ = solve(w64, X0, 1, 0, args.max_iter)
-        st64 = ctx64.stats()
-        ctx64.close()
-        rel = max(abs(a - b) / abs(b) for a, b in zip(out["omega"], out64["omega"]))
-        config["fp64_solve"] = {"s": round(t64[0], 3), "iters": int(st64["iters"]),
-                                "max_rel_omega_diff_vs_mixed": rel}
+        if time.time() + 1.2 * max(times) + 10.0 + 15.0 + cpu_reserve <= deadline:
+            ctx64, out64, t64, _ = solve(w64, X0, 1, 0, args.max_iter)
+            st64 = ctx64.stats()
+            ctx64.close()
+            rel = max(abs(a - b) / abs(b) for a, b in zip(out["omega"], out64["omega"]))
+            config["fp64_solve"] = {"s": round(t64[0], 3), "iters": int(st64["iters"]),
+                                    "applies_fp64": int(st64["applies_fp64"]),
+                                    "phase_ms": {k: round(st64[k], 1) for k in (
+                                        "apply_ms", "precond_ms", "gram_ms", "small_ms", "update_ms", "setup_ms")},
+                                    "max_rel_omega_diff_vs_mixed": rel}
+        else:
+            config["fp64_solve"] = {"skipped": "wall-clock budget"}
     line = {
         "metric": METRIC,
         "value": round(ms / 1000.0, 4),
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": len(times),
+        "warmup": warmup,
         "ms_per_step": round(ms, 2),
         "higher_is_better": False,
         "scaling": "strong",
@@ -527,10 +590,14 @@ def main():
         "roofline_apply": roof_apply,
     }
     if not args.no_cpu_baseline:
-        try:
-            line["cpu_baseline"] = cpu_baseline(w, int(st["iters"]))
-        except Exception as e:  # report, do not hide
-            line["cpu_baseline"] = {"value": None, "error": repr(e)}
+        if time.time() + cpu_reserve <= deadline + 30.0:
+            try:
+                line["cpu_baseline"] = cpu_baseline(w, int(st["iters"]))
+            except Exception as e:  # report, do not hide
+                line["cpu_baseline"] = {"value": None, "error": repr(e)}
+        else:
+            line["cpu_baseline"] = {"value": None, "skipped": "wall-clock budget"}
+    config["wall_s"] = round(time.time() - T_START, 1)
     print(json.dumps(line), flush=True)
 
 

@@ -107,7 +107,7 @@ def ground_state(V, beta_n, beta_s, mass, M, n, L, phi0, tol=1e-12, max_iter=400
         res = spectral.norm(r, h) / np.sqrt(mass)
         if res <= tol:
             break
-        step = np.real(np.fft.ifftn(P * np.fft.fftn(r, axes=axes), axes=axes))
+        step = np.real(spectral.ifftn(P * spectral.fftn(r, axes=axes), axes=axes))
         phi = _normalize(phi - tau * step, h, mass, M)
     mus = np.array([mu + lam, mu, mu - lam])
     E = spin.energy(phi, V, beta_n, beta_s, n, L, h)
@@ -139,7 +139,7 @@ def scalar_ground_state(V, g, n, L, phi0=None, tol=1e-12, max_iter=400000, tau=1
         res = np.sqrt(hd * np.sum(r * r))
         if res <= tol:
             break
-        phi = phi - tau * np.real(np.fft.ifftn(P * np.fft.fftn(r, axes=axes), axes=axes))
+        phi = phi - tau * np.real(spectral.ifftn(P * spectral.fftn(r, axes=axes), axes=axes))
         phi /= np.sqrt(hd * np.sum(phi * phi))
     return phi, float(mu), float(res), it
 

@@ -95,7 +95,7 @@ def _k_apply(op_symbol, X3, grid_shape):
     arr = X3.T.reshape((ncol, 3) + grid_shape)
     d = len(grid_shape)
     axes = tuple(range(-d, 0))
-    out = np.fft.ifftn(op_symbol * np.fft.fftn(arr, axes=axes), axes=axes)
+    out = spectral.ifftn(op_symbol * spectral.fftn(arr, axes=axes), axes=axes)
     return out.reshape(ncol, -1).T
 
 

@@ -14,7 +14,23 @@ second derivative of band-limited trigonometric polynomials.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft
+
+# host threads for the FFTs: the OpenMP thread count when one is set, else every core
+WORKERS = max(1, int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1))
+
+
+def fftn(F: np.ndarray, axes) -> np.ndarray:
+    """Unnormalized forward DFT over ``axes`` (pocketfft, WORKERS threads)."""
+    return scipy.fft.fftn(F, axes=axes, workers=WORKERS)
+
+
+def ifftn(F: np.ndarray, axes) -> np.ndarray:
+    """Inverse DFT over ``axes`` with the 1/N factor (pocketfft, WORKERS threads)."""
+    return scipy.fft.ifftn(F, axes=axes, workers=WORKERS)
 
 
 def wavenumbers(n: int, L: float) -> np.ndarray:
@@ -35,7 +51,7 @@ def kinetic_apply(F: np.ndarray, n, L) -> np.ndarray:
     d = len(n)
     axes = tuple(range(-d, 0))
     sym = kinetic_symbol(n, L)
-    return np.fft.ifftn(sym * np.fft.fftn(F, axes=axes), axes=axes)
+    return ifftn(sym * fftn(F, axes=axes), axes=axes)
 
 
 def kinetic_matrix_1d(n: int, L: float) -> np.ndarray:
