@@ -63,6 +63,8 @@ class BdgContext:
         self.precision = Precision(precision)
         self.grid_shape = tuple(reversed(self.n))
         self.device = V.device
+        if tuple(V.shape) != self.grid_shape:
+            raise ValueError(f"V: expected shape {self.grid_shape}, got {tuple(V.shape)}")
         self._V = V.to(torch.float64).contiguous()
         pr = _lib.Problem()
         pr.dim = self.dim
@@ -116,15 +118,24 @@ class BdgContext:
         mu = (ctypes.c_double * 3)()
         res = ctypes.c_double()
         its = ctypes.c_int()
-        p0 = None if phi0 is None else phi0.to(torch.float64).contiguous()
+        p0 = None
+        if phi0 is not None:
+            self._check_field(phi0, "phi0", 3)
+            p0 = phi0.to(device=self.device, dtype=torch.float64).contiguous()
         st = self._lib.bdg_ground_state(self._h, ctypes.c_void_p(_ptr(p0)), tol, max_iter,
                                         ctypes.c_void_p(_ptr(phi)), mu, ctypes.byref(res), ctypes.byref(its))
         if check:
             self._check(st, "bdg_ground_state")
         return phi, [mu[0], mu[1], mu[2]], res.value, its.value
 
+    def _check_field(self, t, name, lead):
+        want = (lead,) + self.grid_shape
+        if tuple(t.shape) != want:
+            raise ValueError(f"{name}: expected shape {want}, got {tuple(t.shape)}")
+
     def set_ground_state(self, phi, mu):
         torch = _torch()
+        self._check_field(phi, "phi", 3)
         self._phi = phi.to(device=self.device, dtype=torch.float64).contiguous()
         m = (ctypes.c_double * 3)(*[float(v) for v in mu])
         self._check(self._lib.bdg_set_ground_state(self._h, ctypes.c_void_p(_ptr(self._phi)), m),
@@ -133,19 +144,30 @@ class BdgContext:
     def set_ground_state_complex(self, phi, mu):
         """Install a complex ground state (3, *grid) complex128 with chemical potentials mu."""
         torch = _torch()
+        self._check_field(phi, "phi", 3)
         self._phic = phi.to(device=self.device, dtype=torch.complex128).contiguous()
         m = (ctypes.c_double * 3)(*[float(v) for v in mu])
         self._check(self._lib.bdg_set_ground_state_complex(self._h, ctypes.c_void_p(_ptr(self._phic)), m),
                     "bdg_set_ground_state_complex")
 
+    def _check_block(self, X, name, dtype, rows=None, comps=6):
+        """X must be a contiguous device tensor of `dtype` with shape (rows, comps, *grid)
+        (rows: any count when None).  Checked before any pointer reaches the library."""
+        if X.dtype != dtype:
+            raise ValueError(f"{name}: expected {dtype}, got {X.dtype}")
+        want = ((X.shape[0] if rows is None else rows), comps) + self.grid_shape
+        if X.dim() != 2 + self.dim or tuple(X.shape) != want:
+            raise ValueError(f"{name}: expected shape {want}, got {tuple(X.shape)}")
+        if X.device != self.device:
+            raise ValueError(f"{name}: expected a tensor on {self.device}")
+
     def apply(self, X, form: Form = Form.FG, transpose: bool = False, out=None):
         """Y = H X for a block X of shape (b, 6, *grid) (complex128, or complex64 in FP32_APPLY)."""
         torch = _torch()
-        if X.dtype != self.vector_dtype():
-            raise ValueError(f"expected {self.vector_dtype()}")
-        if X.shape[-len(self.grid_shape):] != self.grid_shape or X.shape[-self.dim - 1] != 6:
-            raise ValueError("expected shape (b, 6, *grid)")
-        nvec = X.numel() // (6 * self.npts)
+        self._check_block(X, "X", self.vector_dtype())
+        nvec = X.shape[0]
+        if out is not None:
+            self._check_block(out, "out", self.vector_dtype(), rows=nvec)
         Y = torch.empty_like(X) if out is None else out
         self._check(self._lib.bdg_apply(self._h, int(form), int(bool(transpose)), nvec,
                                         ctypes.c_void_p(_ptr(X)), ctypes.c_void_p(_ptr(Y))), "bdg_apply")
@@ -153,7 +175,10 @@ class BdgContext:
 
     def biortho(self, F, G):
         """In-place bi-orthogonalization of F, G (nvec, 3, *grid) complex128; returns (sigma, rank)."""
+        torch = _torch()
         nvec = F.shape[0]
+        self._check_block(F, "F", torch.complex128, comps=3)
+        self._check_block(G, "G", torch.complex128, rows=nvec, comps=3)
         sig = (ctypes.c_double * nvec)()
         rank = ctypes.c_int()
         self._check(self._lib.bdg_biortho(self._h, nvec, ctypes.c_void_p(_ptr(F)), ctypes.c_void_p(_ptr(G)),
@@ -172,6 +197,7 @@ class BdgContext:
         x0 = None
         if X0 is not None:
             x0 = X0.to(device=self.device, dtype=torch.complex128).contiguous()
+            self._check_block(x0, "X0", torch.complex128, rows=block)
         st = self._lib.bdg_eigs(self._h, k, block, tol, max_iter, ctypes.c_void_p(_ptr(x0)), seed, om,
                                 ctypes.c_void_p(_ptr(uv)), res, ctypes.byref(its))
         if check:
@@ -182,11 +208,15 @@ class BdgContext:
         """d omega_j / d V(x) (k, *grid), d omega_j / d beta_n, d omega_j / d beta_s."""
         torch = _torch()
         k = len(omega)
+        if uv.shape[0] < k:
+            raise ValueError(f"uv: {uv.shape[0]} rows for {k} eigenvalues")
+        uv = uv[:k].contiguous()
+        self._check_block(uv, "uv", torch.complex128, rows=k)
         om = (ctypes.c_double * k)(*omega)
         dV = torch.empty((k,) + self.grid_shape, dtype=torch.float64, device=self.device)
         dbn = (ctypes.c_double * k)()
         dbs = (ctypes.c_double * k)()
-        self._check(self._lib.bdg_eigs_grad(self._h, k, om, ctypes.c_void_p(_ptr(uv.contiguous())),
+        self._check(self._lib.bdg_eigs_grad(self._h, k, om, ctypes.c_void_p(_ptr(uv)),
                                             ctypes.c_void_p(_ptr(dV)), dbn, dbs), "bdg_eigs_grad")
         return dV, list(dbn), list(dbs)
 
@@ -198,7 +228,12 @@ class BdgContext:
         out = torch.empty((nm, nt, 3) + self.grid_shape, dtype=torch.float64, device=self.device)
         om = (ctypes.c_double * max(nm, 1))(*[float(v) for v in omega])
         ts = (ctypes.c_double * max(nt, 1))(*[float(v) for v in t])
-        u = uv.to(dtype=torch.complex128).contiguous() if nm else None
+        u = None
+        if nm:
+            if uv.shape[0] < nm:
+                raise ValueError(f"uv: {uv.shape[0]} rows for {nm} modes")
+            u = uv[:nm].to(dtype=torch.complex128).contiguous()
+            self._check_block(u, "uv", torch.complex128, rows=nm)
         self._check(self._lib.bdg_perturbed_density(self._h, nm, om, ctypes.c_void_p(_ptr(u)), float(eps), nt, ts,
                                                     ctypes.c_void_p(_ptr(out))), "bdg_perturbed_density")
         return out
