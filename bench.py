@@ -2,7 +2,8 @@
 
 One step = one full bdg_eigs solve (deflation set-up, subspace iteration with the FFT apply,
 bi-orthogonalization, Rayleigh-Ritz, updates, float64 certification) from the seed-0
-complex-normal start block to residual <= tol for all k wanted pairs.  The ground state is
+complex-normal start block (for the real ground state of these workloads the library iterates
+on real vectors, Re + Im of each start vector) to residual <= tol for all k wanted pairs.  The ground state is
 computed on the GPU (bdg_ground_state) before the timed region; inputs are resident in HBM.
 
 Default workload: the 3-D trap, 128^3 grid on [-8, 8]^3, V = (x^2 + y^2 + 4 z^2)/2,
@@ -14,9 +15,9 @@ runs, and timed solves stop once another one would not leave room for the float6
 the roofline launches and the CPU baseline; "steps" reports the solves actually timed
 (config.steps_requested the number asked for).
 
-Prints ONE JSON line.  ``roofline`` is the Gram kernel (k_gram, the largest kernel-time
-share of the solve) against the FP64 matrix peak; ``roofline_apply`` is the BdG apply against
-the HBM peak.  Both are timed live with HIP events on the context stream at the solve's own
+Prints ONE JSON line.  ``roofline`` is the Gram kernel of the solve (k_gram_pair, the real
+Gram matrices of the paired form) against the FP64 matrix peak; ``roofline_apply`` is the BdG
+apply against the HBM peak (also reported for float64 vectors and at the 256^3 shape).  Both are timed live with HIP events on the context stream at the solve's own
 shapes.  ``--kernels-only`` runs just those launches (plus a 1 GiB device copy as the
 traffic reference) for counter collection under rocprofv3.
 """
@@ -103,26 +104,28 @@ def _traffic(key, workload_name):
 
 
 def gram_launch(ctx, w, reps=5):
-    """One Rayleigh-Ritz Gram of the solve: M_r = S^H (H S) with m = 3 block columns of
-    K = 3 npts complex rows (Hermitian result, distinct operands).  Algorithmic flops:
-    m (m + 1) / 2 complex entries x 8 K."""
+    """One Rayleigh-Ritz Gram of the solve in its paired real form: M_r = S^T (H S) with
+    m = 3 block real columns (m / 2 complex columns, two real vectors each) over K = 3 npts
+    rows (symmetric result, distinct operands).  Algorithmic flops: m (m + 1) / 2 real
+    entries x 2 K."""
     import torch
     K, m = 3 * w.npts, 3 * w.block
+    mc = m // 2
     g = torch.Generator(device="cuda").manual_seed(0)
-    A = torch.randn((m, K), dtype=torch.complex128, device="cuda", generator=g)
+    A = torch.randn((mc, K), dtype=torch.complex128, device="cuda", generator=g)
     d = torch.rand((K,), dtype=torch.float64, device="cuda", generator=g) + 0.5
     B = A * d
     C = torch.empty((m, m), dtype=torch.complex128, device="cuda")
     lib = ctx._lib
 
     def run():
-        st = lib.bdg_test_gram(ctx._h, K, m, m, ctypes.c_void_p(A.data_ptr()), K, ctypes.c_void_p(B.data_ptr()),
-                               K, 1.0, ctypes.c_void_p(C.data_ptr()), m, 1)
+        st = lib.bdg_test_gram_pair(ctx._h, K, mc, mc, ctypes.c_void_p(A.data_ptr()), K,
+                                    ctypes.c_void_p(B.data_ptr()), K, 1.0, ctypes.c_void_p(C.data_ptr()), m, 1)
         if st != 0:
-            raise RuntimeError(f"bdg_test_gram failed with status {st}")
+            raise RuntimeError(f"bdg_test_gram_pair failed with status {st}")
 
     ms = _event_ms(ctx.stream, run, reps)
-    flops = 4.0 * K * m * (m + 1)
+    flops = 1.0 * K * m * (m + 1)
     del A, B, C, d
     torch.cuda.empty_cache()
     return ms, flops
@@ -143,6 +146,30 @@ def apply_launch(ctx, w, reps=10):
     del X, Y
     torch.cuda.empty_cache()
     return ms, nbytes
+
+
+def apply_launch_large(reps=3):
+    """bdg_apply at the 256^3 lattice trap's shape (64 complex64 vectors, the block of the
+    largest configuration: X and Y 51.5 GB each).  Only the operator is exercised, so any real
+    ground state serves (the initial spinor of the flow)."""
+    import torch
+    from paper_2506_08308_amd import BdgContext, Precision
+    w = W.C5
+    V = torch.from_numpy(W.potential(w)).to("cuda")
+    ctx = BdgContext(w.dim, w.n, w.L, V, w.beta_n, w.beta_s, w.mass, w.magnetization, Precision.FP32_APPLY)
+    ctx.set_ground_state(torch.from_numpy(W.initial_spinor(w)).to("cuda"), [1.0, 1.0, 1.0])
+    del V
+    ms, nbytes = apply_launch(ctx, w, reps=reps)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return ms, nbytes
+
+
+def _apply_roof(ms, nbytes, label):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "kernel": label, "ms_per_launch": round(ms, 3),
+            "algorithmic_bytes": nbytes}
 
 
 def copy_reference(reps=3):
@@ -476,6 +503,126 @@ def campaign_complex(n=256, L=12.0, beta_n=200.0, beta_s=80.0, k=32, block=48, t
           flush=True)
 
 
+# Section 4.2, Example "3D Case": Bogoliubov amplitudes of the l-th mode at h = 1/8 on [-8, 8]^3;
+# Case I ferromagnetic isotropic (l = 25), II antiferromagnetic isotropic (26), III
+# ferromagnetic with gamma_z = 2 gamma_x = 2 gamma_y (62), IV antiferromagnetic, same trap (42);
+# l counts the ascending eigenvalues from 1, M = 0 (the paper does not state M).
+AMPLITUDE_CASES = [("I", "harmonic3", "FM", 25), ("II", "harmonic3", "AFM", 26),
+                   ("III", "harmonic3_z2", "FM", 62), ("IV", "harmonic3_z2", "AFM", 42)]
+FIELD_NAMES = ("u_1", "u_0", "u_-1", "v_1", "v_0", "v_-1")
+
+
+def campaign_amplitudes(n=128, L=8.0, tol=1e-9):
+    """The paper's figures show isosurfaces of u_j^l and v_j^l; the campaign reports, for the
+    l-th mode and every member of its degenerate cluster, the per-field norm, maximum, second
+    moments along x, y, z (the compression along the stiffer axis) and reflection parities
+    (bdg_mode_amplitudes), with the amplitude kernel's time over all computed modes."""
+    import torch
+    for case, pot, kind, ell in AMPLITUDE_CASES:
+        bn, bs = CAMPAIGN_BETAS[kind]
+        k = ell + 4
+        w = W.Workload(f"amp_{case}_{kind}_{n}", 3, (n,) * 3, (L,) * 3, pot, bn, bs, 0.0, k=k, block=k + 16)
+        log(f"amplitudes {w.name}")
+        ctx = _context(w)
+        t0 = time.time()
+        _ground_state(ctx)
+        out = ctx.eigs(k, w.block, tol=tol, max_iter=1500, seed=0, check=False)
+        om = out["omega"]
+        j = ell - 1
+        members = [i for i in range(k) if abs(om[i] - om[j]) <= 1e-8 * om[j]]
+        summ = ctx.mode_amplitudes(out["uv"][members])
+        ms = _event_ms(ctx.stream, lambda: ctx.mode_amplitudes(out["uv"]), 3)
+        nbytes = k * 6 * w.npts * 16
+        modes_out = []
+        for i, s_l in zip(members, summ):
+            modes_out.append({"index": i + 1, "omega": om[i], "fields": {
+                FIELD_NAMES[f]: {"norm": s_l[f][0], "max": s_l[f][1], "x2": s_l[f][2:5], "parity": s_l[f][5:8]}
+                for f in range(6)}})
+        ctx.close()
+        print(json.dumps({"campaign": "amplitudes", "case": case, "kind": kind, "trap": pot, "N": n,
+                          "h": 2 * L / n, "l": ell, "eig_status": out["status"], "eig_iters": out["iters"],
+                          "max_residual": max(out["residual"]), "seconds": round(time.time() - t0, 1),
+                          "cluster": modes_out,
+                          "amplitude_kernel": {"modes": k, "ms": round(ms, 3),
+                                               "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}}), flush=True)
+
+
+def _cluster_means(vals, omega, tol=1e-8):
+    """Each member of a cluster |omega_i - omega_j| <= tol omega gets the cluster mean (the
+    derivative of a degenerate eigenvalue is defined for the cluster's mean only)."""
+    vals = np.array(vals, dtype=float)
+    out = vals.copy()
+    j0 = 0
+    while j0 < len(omega):
+        j1 = j0 + 1
+        while j1 < len(omega) and abs(omega[j1] - omega[j0]) <= tol * abs(omega[j0]):
+            j1 += 1
+        out[j0:j1] = vals[j0:j1].mean(axis=0)
+        j0 = j1
+    return out
+
+
+def campaign_grad(ndir=32, eps=1e-6):
+    """Gradients of the 16 lowest frequencies of the 2-D 256^2 lattice trap (beta_s = -2
+    primary, +2 secondary) with respect to V(x), beta_n and beta_s (bdg_eigs_grad: left/right
+    eigenvector form plus the ground-state sensitivity), against central differences of the
+    whole GPU pipeline (ground state to 1e-13, eigensolve to 1e-10) along `ndir` seeded
+    directions dV ~ N(0, 1) per point, d beta_n, d beta_s ~ N(0, 1), step eps.  k is widened
+    past a degenerate pair at 16; relative error |FD - adjoint| / |FD| (absolute over
+    ||grad|| ||dir|| where |FD| < 1e-3 ||grad|| ||dir||)."""
+    import torch
+    for w in (W.C4, W.C4_POLAR):
+        V = W.potential(w)
+        X0 = torch.from_numpy(W.start_block(w)).to("cuda")
+        kq = w.k + 2
+
+        def pipeline(Vx, bn, bs, k_use=None):
+            ww = w.with_(beta_n=bn, beta_s=bs)
+            from paper_2506_08308_amd import BdgContext, Precision
+            ctx = BdgContext(ww.dim, ww.n, ww.L, torch.from_numpy(np.ascontiguousarray(Vx)).to("cuda"), bn, bs,
+                             ww.mass, ww.magnetization, Precision.FP64)
+            ctx.ground_state(tol=ww.gs_tol, max_iter=400000)
+            out = ctx.eigs(kq, ww.block, tol=ww.tol, max_iter=3000, X0=X0)
+            om = np.array(out["omega"])
+            g, g_ms = None, None
+            if k_use is not None:
+                torch.cuda.synchronize()
+                t0 = time.time()
+                g = ctx.eigs_grad(list(om[:k_use]), out["uv"][:k_use].contiguous())
+                torch.cuda.synchronize()
+                g_ms = 1000.0 * (time.time() - t0)
+            ctx.close()
+            return om, g, g_ms
+
+        om, _, _ = pipeline(V, w.beta_n, w.beta_s)
+        k_use = w.k
+        while k_use < kq and abs(om[k_use] - om[k_use - 1]) <= 1e-8 * om[k_use - 1]:
+            k_use += 1
+        om, (dV, dbn, dbs), g_ms = pipeline(V, w.beta_n, w.beta_s, k_use)
+        om = om[:k_use]
+        dV = dV.cpu().numpy()
+        hd = float(np.prod(w.h))
+        gnorm = np.array([np.sqrt(hd * np.sum(dV[j] ** 2) + dbn[j] ** 2 + dbs[j] ** 2) for j in range(k_use)])
+        worst, per_dir = 0.0, []
+        t0 = time.time()
+        for seed in range(ndir):
+            dVd, dbnd, dbsd = W.fd_direction(w, seed)
+            op, _, _ = pipeline(V + eps * dVd, w.beta_n + eps * dbnd, w.beta_s + eps * dbsd)
+            omm, _, _ = pipeline(V - eps * dVd, w.beta_n - eps * dbnd, w.beta_s - eps * dbsd)
+            fd = _cluster_means((op[:k_use] - omm[:k_use]) / (2 * eps), om)
+            ad = np.array([hd * np.sum(dV[j] * dVd) + dbn[j] * dbnd + dbs[j] * dbsd for j in range(k_use)])
+            dnorm = np.sqrt(hd * np.sum(dVd ** 2) + dbnd ** 2 + dbsd ** 2)
+            err = np.where(np.abs(fd) >= 1e-3 * gnorm * dnorm, np.abs(fd - ad) / np.abs(fd),
+                           np.abs(fd - ad) / (gnorm * dnorm))
+            per_dir.append(float(err.max()))
+            worst = max(worst, float(err.max()))
+            log(f"grad {w.name} direction {seed}: max rel err {err.max():.2e}")
+        print(json.dumps({"campaign": "grad", "workload": w.name, "grid": list(w.n), "beta_s": w.beta_s,
+                          "k": k_use, "directions": ndir, "eps": eps, "max_rel_err": worst,
+                          "per_direction_max_rel_err": per_dir, "bound": 1e-5, "pass": worst <= 1e-5,
+                          "eigs_grad_ms": round(g_ms, 1), "fd_seconds": round(time.time() - t0, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,7 +637,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 solve timed beside the mixed one")
     ap.add_argument("--kernels-only", action="store_true")
-    ap.add_argument("--campaign", choices=("accuracy", "efficiency", "modes", "complex"),
+    ap.add_argument("--campaign", choices=("accuracy", "efficiency", "modes", "complex", "grad", "amplitudes"),
                     help="the paper's accuracy (Kohn modes vs h) or efficiency (time vs DOF) campaign, or its "
                          "perturbed-density example")
     ap.add_argument("--campaign-dims", default="1,2,3", help="comma-separated dimensions to run")
@@ -520,7 +667,14 @@ def main():
     if args.campaign == "complex":
         campaign_complex()
         return
+    if args.campaign == "grad":
+        campaign_grad()
+        return
+    if args.campaign == "amplitudes":
+        campaign_amplitudes()
+        return
     deadline = T_START + args.budget_s
+    line_extra = {}
     cpu_reserve = 0.0 if args.no_cpu_baseline else CPU_BASELINE_RESERVE_S
     warmup = min(args.warmup, 1)
     X0 = torch.from_numpy(W.start_block(w)).to("cuda")
@@ -528,7 +682,7 @@ def main():
     def reserve(step_s):
         # what must still fit after the last timed solve: the float64 solve beside it, the
         # roofline launches and the CPU baseline
-        return (1.2 * step_s + 10.0 if w64 is not None else 0.0) + 15.0 + cpu_reserve
+        return (1.2 * step_s + 10.0 if w64 is not None else 0.0) + 35.0 + cpu_reserve
 
     # the reserve depends on the step time, known after the first solve; solve() checks
     # before each further timed solve
@@ -543,7 +697,8 @@ def main():
     a_gbs = a_bytes / (a_ms * 1e-3) / 1e9
     roof = {"bound": "mfma", "achieved": round(g_tfs, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
             "frac": round(g_tfs / FP64_MFMA_PEAK_TFS, 4), "traffic": _traffic("gram", w.name),
-            "kernel": f"k_gram: Rayleigh-Ritz Gram S^H (H S), {3 * w.block} columns x {3 * w.npts} rows, FP64 MFMA",
+            "kernel": f"k_gram_pair: Rayleigh-Ritz Gram S^T (H S) of {3 * w.block} real columns (paired, "
+                      f"{3 * w.block // 2} complex) x {3 * w.npts} rows, FP64 MFMA",
             "ms_per_launch": round(g_ms, 3), "algorithmic_flops": g_flops}
     roof_apply = {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(a_gbs / HBM_PEAK_GBS, 4), "traffic": _traffic("apply", w.name),
@@ -563,6 +718,9 @@ def main():
         if time.time() + 1.2 * max(times) + 10.0 + 15.0 + cpu_reserve <= deadline:
             ctx64, out64, t64, _ = solve(w64, X0, 1, 0, args.max_iter)
             st64 = ctx64.stats()
+            a64_ms, a64_bytes = apply_launch(ctx64, w64, reps=5)
+            line_extra["roofline_apply_fp64"] = _apply_roof(
+                a64_ms, a64_bytes, f"bdg_apply on {w64.block} complex128 vectors, {list(w64.n)} grid")
             ctx64.close()
             rel = max(abs(a - b) / abs(b) for a, b in zip(out["omega"], out64["omega"]))
             config["fp64_solve"] = {"s": round(t64[0], 3), "iters": int(st64["iters"]),
@@ -589,6 +747,14 @@ def main():
         "roofline": roof,
         "roofline_apply": roof_apply,
     }
+    line.update(line_extra)
+    if time.time() + 20.0 + cpu_reserve <= deadline + 30.0:
+        try:
+            c5_ms, c5_bytes = apply_launch_large()
+            line["roofline_apply_256"] = _apply_roof(
+                c5_ms, c5_bytes, f"bdg_apply on {W.C5.block} complex64 vectors, {list(W.C5.n)} grid")
+        except Exception as e:  # report, do not hide
+            line["roofline_apply_256"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         if time.time() + cpu_reserve <= deadline + 30.0:
             try:

@@ -134,8 +134,11 @@ bdg_status bdg_biortho(bdg_ctx* ctx, int nvec, void* F_dev, void* G_dev, double*
  * checked with a float64 apply at the end; the second term is the float64 rounding floor of
  * this relative residual (eps = DBL_EPSILON, ||H|| bounded by the largest kinetic symbol plus
  * the largest pointwise row sum of H_+-), so `residual` may exceed a tol below that floor.
- * X0_dev: block x 6 npts complex128 start block in (f, g) form (NULL = complex normal
- * block drawn from `seed`).  omega (host, k): ascending; UV_dev (device, k x 6 npts
+ * For a real ground state the operator is real and the iteration runs on real trial vectors
+ * (two to a complex column inside the library; the block is rounded up to an even count):
+ * X0_dev: block x 6 npts complex128 start block in (f, g) form whose vector j contributes the
+ * real start vector Re + Im (NULL = real normal vectors drawn from `seed`); the eigenvectors
+ * come back real (zero imaginary parts).  omega (host, k): ascending; UV_dev (device, k x 6 npts
  * complex128): eigenvectors in (u, v) form with int |u|^2 - |v|^2 = 1 (i.e. <f, g> = 1/4);
  * may be NULL.  residual (host, k), iters (host) may be NULL.  Needs
  * 1 <= k <= block <= min(160, 3 npts - 4) (each half of a trial vector lives in 3 npts
@@ -170,6 +173,21 @@ bdg_status bdg_eigs_grad(bdg_ctx* ctx, int k, const double* omega, const void* U
  * Synchronizes the context stream before returning. */
 bdg_status bdg_perturbed_density(bdg_ctx* ctx, int nmodes, const double* omega, const void* UV_dev,
                                  double eps, int nt, const double* t, void* out_dev);
+
+/* Bogoliubov-amplitude summaries of normal modes (Section 4.2, Applications: the 3-D example
+ * shows isosurfaces of the amplitudes u_j^l, v_j^l and remarks on their symmetry under
+ * reflections of the trap and their compression along its stiffer axis; these are the numbers
+ * behind such remarks).  For nmodes vectors in (u, v) form (UV_dev, device, nmodes x 6 npts
+ * complex128, as bdg_eigs returns them) and each of their six fields w = u_1, u_0, u_-1, v_1,
+ * v_0, v_-1, out (host, nmodes x 6 x 8 doubles, mode-major, then field) receives
+ *   [0] h^d sum |w|^2,  [1] max |w|,
+ *   [2 + a] h^d sum x_a^2 |w|^2 / [0]                  (a = x, y, z; 0 beyond dim),
+ *   [5 + a] Re h^d sum w(x) conj(w(R_a x)) / [0]        (0 beyond dim),
+ * with x_a = -L_a + m h_a on the grid and R_a the reflection x_a -> -x_a (grid index
+ * m -> (N_a - m) mod N_a): +1 for a field even under R_a, -1 for an odd one.  Entries 2..7 are
+ * 0 for a zero field.  nmodes = 0 is a no-op; BDG_EINVAL on a negative count, null pointers or
+ * nmodes > 10922.  Needs no ground state.  Synchronous; deterministic (fixed reduction order). */
+bdg_status bdg_mode_amplitudes(bdg_ctx* ctx, int nmodes, const void* UV_dev, double* out);
 
 /* Per-phase timers and counters of the last bdg_eigs call (milliseconds from HIP events):
  * out[0] total, out[1] apply, out[2] preconditioner, out[3] Gram matrices, out[4] small

@@ -26,6 +26,19 @@ bdg_status bdg_test_gram(bdg_ctx* ctx, long long K, int m1, int m2, const void* 
 bdg_status bdg_test_update(bdg_ctx* ctx, long long K, int m, const void* S, long long lds,
                            const void* Cm, int ldcm, int nb, double beta, void* Y, long long ldy);
 
+/* Paired real form (two real columns per complex column: real part 2 j, imaginary part
+ * 2 j + 1).  C (2 m1 x 2 m2 real entries stored as complex with zero imaginary parts, ldc >= 2 m1)
+ * = alpha * Ar^T Br for A: K x m1 complex columns (lda), B: K x m2 (ldb).  symmetric = 1
+ * declares Ar^T Br symmetric (needs m1 == m2): upper tiles, mirrored. */
+bdg_status bdg_test_gram_pair(bdg_ctx* ctx, long long K, int m1, int m2, const void* A, long long lda,
+                              const void* B, long long ldb, double alpha, void* C, int ldc, int symmetric);
+
+/* Paired real form: Y (nb real columns = nb / 2 complex columns, ldy) = S (2 m real columns =
+ * m complex columns, lds) * Cm (2 m x nb real coefficients stored as complex, only the real
+ * parts are read, ldcm >= 2 m) + beta * Y; nb even. */
+bdg_status bdg_test_update_pair(bdg_ctx* ctx, long long K, int m, const void* S, long long lds, const void* Cm,
+                                int ldcm, int nb, double beta, void* Y, long long ldy);
+
 /* One-sided Jacobi SVD of G (rows x m, ldg), m <= 512: G is replaced by U diag(s) with
  * columns ordered by descending s; V (m x m, ldv) receives V; s (device, m). */
 bdg_status bdg_test_svd(bdg_ctx* ctx, int rows, int m, void* G, int ldg, void* V, int ldv, void* s);

@@ -29,6 +29,9 @@ following steps, each in plain numpy:
               = L_K L_K^H; the projected problem K~ b = omega a, M~ a = omega b is
               solved by the SVD L_K^H L_M = U_G diag(omega) V_G^H: a = L_K u, b = L_M v;
   update      F <- S_f C_f a, G <- S_g C_g b (and their images), P from the W and P rows;
+              the images of F and G are recomputed from F and G every 20 iterations; a
+              projected problem that is not numerically definite is solved again with every
+              image recomputed, then without P;
   stop        when res_j <= tol for the k wanted columns, with
               res_j = ||(H_- g_j - w_j f_j, H_+ f_j - w_j g_j)|| / (|w_j| ||(f_j, g_j)||).
 
@@ -222,6 +225,19 @@ def _orth_factor(S, hd, rtol):
 
 
 def rayleigh_ritz(Sf, Sg, HSf, HSg, nkeep, hd, eps=1e-10, rtol=1e-14):
+    """``_rayleigh_ritz_once`` with escalating cut-offs: rounding in the projected matrices can
+    make them indefinite along nearly dependent directions of the basis (the Cholesky factor
+    then does not exist); the step is repeated with both cut-offs raised 100x, at most twice.
+    Dropping those directions leaves the part of the span that carries the wanted pairs."""
+    for attempt in range(3):
+        try:
+            return _rayleigh_ritz_once(Sf, Sg, HSf, HSg, nkeep, hd, eps * 100.0 ** attempt, rtol * 100.0 ** attempt)
+        except np.linalg.LinAlgError:
+            if attempt == 2:
+                raise
+
+
+def _rayleigh_ritz_once(Sf, Sg, HSf, HSg, nkeep, hd, eps, rtol):
     """Bi-orthogonalize, project, solve; returns (omega, a, b) with F = Sf a, G = Sg b.
 
     Each basis is first made orthonormal on its own (dropping numerically dependent
@@ -273,6 +289,9 @@ def lrep_eigs(prob: LrepProblem, k: int, X0: np.ndarray, tol: float, max_iter: i
     it = 0
     res = np.full(b, np.inf)
     for it in range(1, max_iter + 1):
+        if it % 20 == 0:
+            # images by recurrence drift from H applied to the basis; recompute them
+            HF, HG = prob.hplus(F), prob.hminus(G)
         Rf = HG - F * om          # H_- g - omega f
         Rg = HF - G * om          # H_+ f - omega g
         num = np.sqrt(np.sum(np.abs(Rf) ** 2, axis=0) + np.sum(np.abs(Rg) ** 2, axis=0))
@@ -292,7 +311,23 @@ def lrep_eigs(prob: LrepProblem, k: int, X0: np.ndarray, tol: float, max_iter: i
         hparts_g = [HG, HWg] + ([HPg] if HPg is not None else [])
         Sf, Sg = np.hstack(parts_f), np.hstack(parts_g)
         HSf, HSg = np.hstack(hparts_f), np.hstack(hparts_g)
-        om, a, bb = rayleigh_ritz(Sf, Sg, HSf, HSg, b, hd)
+        try:
+            om, a, bb = rayleigh_ritz(Sf, Sg, HSf, HSg, b, hd)
+        except np.linalg.LinAlgError:
+            # the projected problem lost definiteness along nearly dependent directions of
+            # [F, W, P]: recompute every image from its vector, and if that is not enough
+            # restart the step from [F, W] (the eigenpairs do not depend on the path)
+            hparts_f = [prob.hplus(x) for x in parts_f]
+            hparts_g = [prob.hminus(x) for x in parts_g]
+            HSf, HSg = np.hstack(hparts_f), np.hstack(hparts_g)
+            try:
+                om, a, bb = rayleigh_ritz(Sf, Sg, HSf, HSg, b, hd)
+            except np.linalg.LinAlgError:
+                if Pf is None:
+                    raise
+                Sf, Sg = np.hstack(parts_f[:2]), np.hstack(parts_g[:2])
+                HSf, HSg = np.hstack(hparts_f[:2]), np.hstack(hparts_g[:2])
+                om, a, bb = rayleigh_ritz(Sf, Sg, HSf, HSg, b, hd)
         Pf, Pg = Sf[:, b:] @ a[b:], Sg[:, b:] @ bb[b:]
         HPf, HPg = HSf[:, b:] @ a[b:], HSg[:, b:] @ bb[b:]
         # unit columns for P as well; the images scale with them

@@ -254,10 +254,10 @@ def product_branch(h0: ScalarOp, hx: ScalarOp, phi, k: int, tol: float, nb: Opti
     pK = lambda C: cols(T0(fields(C)))
     pM = lambda C: cols(Tx(fields(C)))
     ph = np.asarray(phi, dtype=np.float64).reshape(-1, 1)
-    Nx = ph / np.sqrt(hd * float(ph.T @ ph))
+    Nx = ph / np.sqrt(hd * float((ph.T @ ph)[0, 0]))
     proj_x = lambda C: C - Nx @ (hd * (Nx.T @ C))
     phat, _ = lrep.projected_cg(opM, Nx.copy(), lambda v: v, pM, 1e-14)
-    Ny = phat / np.sqrt(hd * float(phat.T @ phat))
+    Ny = phat / np.sqrt(hd * float((phat.T @ phat)[0, 0]))
     proj_y = lambda C: C - Ny @ (hd * (Ny.T @ C))
     rng = np.random.default_rng(seed)
     X = proj_x(rng.standard_normal((grid.npts, nb)))

@@ -15,8 +15,9 @@ BDG_FORM_UV, BDG_FORM_FG = 0, 1
 EXPORTS = ("bdg_create", "bdg_destroy", "bdg_last_error", "bdg_ground_state", "bdg_set_ground_state",
            "bdg_set_ground_state_complex", "bdg_apply", "bdg_biortho", "bdg_eigs", "bdg_eigs_grad",
            "bdg_perturbed_density", "bdg_stats",
+           "bdg_mode_amplitudes",
            "bdg_test_gram", "bdg_test_update", "bdg_test_svd", "bdg_test_cholesky", "bdg_test_pchol",
-           "bdg_test_plu")
+           "bdg_test_plu", "bdg_test_gram_pair", "bdg_test_update_pair")
 
 
 class Problem(ctypes.Structure):
@@ -60,6 +61,8 @@ def load() -> ctypes.CDLL:
     lib.bdg_set_ground_state_complex.restype = st
     lib.bdg_perturbed_density.argtypes = [vp, i, pd, vp, d, i, pd, vp]
     lib.bdg_perturbed_density.restype = st
+    lib.bdg_mode_amplitudes.argtypes = [vp, i, vp, pd]
+    lib.bdg_mode_amplitudes.restype = st
     lib.bdg_stats.argtypes = [vp, pd, i]
     lib.bdg_stats.restype = st
     ll = ctypes.c_longlong
@@ -67,6 +70,10 @@ def load() -> ctypes.CDLL:
     lib.bdg_test_gram.restype = st
     lib.bdg_test_update.argtypes = [vp, ll, i, vp, ll, vp, i, i, d, vp, ll]
     lib.bdg_test_update.restype = st
+    lib.bdg_test_gram_pair.argtypes = [vp, ll, i, i, vp, ll, vp, ll, d, vp, i, i]
+    lib.bdg_test_gram_pair.restype = st
+    lib.bdg_test_update_pair.argtypes = [vp, ll, i, vp, ll, vp, i, i, d, vp, ll]
+    lib.bdg_test_update_pair.restype = st
     lib.bdg_test_svd.argtypes = [vp, i, i, vp, i, vp, i, vp]
     lib.bdg_test_svd.restype = st
     lib.bdg_test_cholesky.argtypes = [vp, i, vp, i]

@@ -238,6 +238,20 @@ class BdgContext:
                                                     ctypes.c_void_p(_ptr(out))), "bdg_perturbed_density")
         return out
 
+    def mode_amplitudes(self, uv):
+        """bdg_mode_amplitudes: per mode and field of (u_1, u_0, u_-1, v_1, v_0, v_-1) the norm,
+        max |w|, second moments along x, y, z and reflection parities; (nmodes, 6, 8) list."""
+        torch = _torch()
+        nm = uv.shape[0]
+        if nm == 0:
+            return []
+        u = uv.to(dtype=torch.complex128).contiguous()
+        self._check_block(u, "uv", torch.complex128, rows=nm)
+        out = (ctypes.c_double * (nm * 6 * 8))()
+        self._check(self._lib.bdg_mode_amplitudes(self._h, nm, ctypes.c_void_p(_ptr(u)), out), "bdg_mode_amplitudes")
+        vals = list(out)
+        return [[vals[(l * 6 + f) * 8:(l * 6 + f + 1) * 8] for f in range(6)] for l in range(nm)]
+
     def stats(self):
         out = (ctypes.c_double * 10)()
         self._check(self._lib.bdg_stats(self._h, out, 10), "bdg_stats")

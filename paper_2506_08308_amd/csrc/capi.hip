@@ -418,6 +418,27 @@ bdg_status bdg_test_update(bdg_ctx* c, long long K, int m, const void* S, long l
     return BDG_OK;
 }
 
+bdg_status bdg_test_gram_pair(bdg_ctx* c, long long K, int m1, int m2, const void* A, long long lda, const void* B,
+                              long long ldb, double alpha, void* C, int ldc, int symmetric) {
+    if (!c || !A || !B || !C || K < 1 || m1 < 1 || m2 < 1 || ldc < 2 * m1) return ctx_fail(c, BDG_EINVAL, "bad args");
+    if (symmetric && m1 != m2) return ctx_fail(c, BDG_EINVAL, "symmetric needs m1 == m2");
+    Seg a{A, m1}, b{B, m2};
+    BDG_TRY(gram_seg_pair(c, K, &a, 1, lda, &b, 1, ldb, alpha, (double2*)C, ldc, symmetric));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+
+bdg_status bdg_test_update_pair(bdg_ctx* c, long long K, int m, const void* S, long long lds, const void* Cm, int ldcm,
+                                int nb, double beta, void* Y, long long ldy) {
+    if (!c || !S || !Cm || !Y || K < 1 || m < 1 || nb < 2 || (nb & 1) || ldcm < 2 * m)
+        return ctx_fail(c, BDG_EINVAL, "bad args");
+    Seg s{S, m};
+    BDG_TRY(update_pair(c, K, &s, 1, lds, (const double2*)Cm, ldcm, 0, nb, beta, (const double2*)Y, ldy, (double2*)Y,
+                        ldy));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+
 bdg_status bdg_test_svd(bdg_ctx* c, int rows, int m, void* G, int ldg, void* V, int ldv, void* s) {
     if (!c || !G || !V || !s || m < 1 || m > 512 || rows < 1 || ldg < rows || ldv < m)
         return ctx_fail(c, BDG_EINVAL, "bad args");

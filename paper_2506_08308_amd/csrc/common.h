@@ -168,6 +168,27 @@ bdg_status update(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long 
 bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cm,
                       int ldcm, int nb, double beta, const double2* Z, long long ldz, double2* Y, long long ldy);
 
+// Paired real form (real ground states): each complex column holds two real columns, its real
+// part (real column 2 J) and its imaginary part (2 J + 1).  Segments count complex columns.
+// C (2 m1 x 2 m2 real entries in complex storage, imaginary parts 0, ldc) = alpha Ar^T Br;
+// hermitian != 0: A == B or Ar^T Br symmetric by structure (upper tiles, mirrored).
+bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long long lda, const Seg* sb, int nbs,
+                         long long ldb, double alpha, double2* C, int ldc, int hermitian);
+// Y (nbr real columns) = S (segments, 2 mp real columns) Cr[r0 :, :] (real parts of the complex-stored
+// 2 mp x nbr coefficient matrix Cr, ld ldcr, from row r0) + beta Z; nbr even; Y must not overlap S
+bdg_status update_pair(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cr, int ldcr,
+                       int r0, int nbr, double beta, const double2* Z, long long ldz, double2* Y, long long ldy);
+// squared norms of the 2 ncols real columns of ncols complex columns
+bdg_status colnorm2_pair(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx, double* out_dev);
+// residual norms of the 2 ncols real columns (omega per real column, om_dev[2 ncols]):
+// out_dev[q * 2 ncols + j] holds |HF_j - om_j G_j|^2 (q = 0), |HG_j - om_j F_j|^2 (1), |F_j|^2 (2),
+// |G_j|^2 (3)
+bdg_status resnorm2_pair(bdg_ctx* c, long long K, int ncols, const double2* HF, const double2* G, const double2* HG,
+                         const double2* F, long long ld, const double* om_dev, double* out_dev);
+// out_dev[j] = F_j . G_j over the 2 ncols real columns
+bdg_status dot_pair(bdg_ctx* c, long long K, int ncols, const double2* F, const double2* G, long long ld,
+                    double* out_dev);
+
 // small dense FP64 complex matrices on the device (column-major)
 bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, double2 alpha,
                       const double2* A, int lda, const double2* B, int ldb, double2 beta,
@@ -196,7 +217,4 @@ bdg_status small_plu_biorth(bdg_ctx* c, int p, int q, double2* B, int ldb, doubl
 // column norms squared (deterministic), etc.
 bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx,
                     double* out_dev);
-// residual norms of ncols columns (stride ld) in one pass: out_dev[q * ncols + j] holds
-// |HF_j - om_j G_j|^2 (q = 0), |HG_j - om_j F_j|^2 (1), |F_j|^2 (2), |G_j|^2 (3)
-bdg_status resnorm2(bdg_ctx* c, long long K, int ncols, const double2* HF, const double2* G, const double2* HG,
-                    const double2* F, long long ld, const double* om_dev, double* out_dev);
+

@@ -190,6 +190,136 @@ __global__ void __launch_bounds__(256) k_gram(long long K, int m1, int m2, SegLi
             }
 }
 
+// Paired real form: every complex column holds two real columns (real part, imaginary part),
+// and part[s] receives the real Gram R = Ar^T Br of the 2 m1 and 2 m2 real columns
+// (R[2p + u][2q + v] = sum_k A_u[k, p] B_v[k, q], u, v = 0 for the real, 1 for the imaginary
+// parts), column-major with leading dimension 2 m1.  Same tiles, staging and work order as
+// k_gram (tiles of 64 x 64 complex columns, i.e. 128 x 128 real entries); the MFMAs run over
+// complex rows with the two parts as separate operands, so a tile takes as many MFMAs as a
+// complex tile while covering four real entries per pair of complex columns.
+__global__ void __launch_bounds__(256) k_gram_pair(long long K, int m1, int m2, SegList A, long long lda, SegList B,
+                                                   long long ldb, long long kper, int tn, int herm, int same,
+                                                   int ntiles, long long total, long long per_xcd,
+                                                   double* __restrict__ part) {
+    __shared__ __align__(16) double la[GT * GPAD];
+    __shared__ __align__(16) double lb[GT * GPAD];
+    long long split;
+    int ti, tj;
+    if (!gram_item(blockIdx.x, per_xcd, total, ntiles, tn, herm, &split, &ti, &tj)) return;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const long long ldr = 2LL * m1;
+    double* out = part + split * ldr * (2LL * m2);
+    const bool diag = same && ti == tj;
+    const double* lbr = diag ? la : lb;
+    const int p0 = ti * GT, q0 = tj * GT;
+    const long long k0 = split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const bool idle = herm && ti == tj && wr > wc;
+    // acc[a][b][2 u + v]: real part u of A's block a against part v of B's block b
+    d4 acc[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][b][q] = d4{0, 0, 0, 0};
+    const int lk = t & 15, lc = t >> 4;
+    const double2* acol[4];
+    const double2* bcol[4];
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int col = lc + 16 * pass;
+        acol[pass] = (p0 + col < m1) ? seg_col(A, p0 + col, lda) : nullptr;
+        bcol[pass] = (!diag && q0 + col < m2) ? seg_col(B, q0 + col, ldb) : nullptr;
+    }
+    double2 ra[4], rb[4];
+    auto gload = [&](long long kc) {
+        const long long kk = kc + lk;
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            ra[pass] = (kk < k1 && acol[pass]) ? acol[pass][kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && bcol[pass]) ? bcol[pass][kk] : double2{0, 0};
+        }
+    };
+    gload(k0);
+    for (long long kc = k0; kc < k1; kc += GKC) {
+        __syncthreads();
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const int col = lc + 16 * pass;
+            *reinterpret_cast<double2*>(&la[col * GPAD + 2 * lk]) = ra[pass];
+            if (!diag) *reinterpret_cast<double2*>(&lb[col * GPAD + 2 * lk]) = rb[pass];
+        }
+        __syncthreads();
+        if (kc + GKC < k1) gload(kc + GKC);
+        if (idle) continue;
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < GKC; ks += 4) {
+            const int kr = 2 * (ks + (lane >> 4));  // first double of this lane's complex row
+            const int ci = lane & 15;
+            double2 av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = *reinterpret_cast<const double2*>(&la[(wr + 16 * a + ci) * GPAD + kr]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = *reinterpret_cast<const double2*>(&lbr[(wc + 16 * b + ci) * GPAD + kr]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b][0] = mfma(av[a].x, bv[b].x, acc[a][b][0]);
+                    acc[a][b][1] = mfma(av[a].x, bv[b].y, acc[a][b][1]);
+                    acc[a][b][2] = mfma(av[a].y, bv[b].x, acc[a][b][2]);
+                    acc[a][b][3] = mfma(av[a].y, bv[b].y, acc[a][b][3]);
+                }
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+    if (idle) return;
+    // register r of lane l holds D[4 r + l / 16][l % 16]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + wr + 16 * a + 4 * r + (lane >> 4);
+                const int q = q0 + wc + 16 * b + (lane & 15);
+                if (p < m1 && q < m2) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 2; ++v) out[(2LL * q + v) * ldr + 2 * p + u] = acc[a][b][2 * u + v][r];
+                }
+            }
+}
+
+// C (m1 x m2 real entries in complex storage, imaginary parts 0) = alpha * sum over the splits
+// of the real partials, in split order; herm mirrors every entry below the diagonal 16 x 16
+// blocks from above (the paired tiles compute those blocks, see k_gram_pair)
+__global__ void k_gram_reduce_real(int m1, int m2, int nsplit, const double* __restrict__ part, double alpha,
+                                   double2* __restrict__ C, int ldc, int herm) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)m1 * m2) return;
+    const int p = (int)(idx % m1), q = (int)(idx / m1);
+    const bool mirror = herm && (p / 16) > (q / 16);
+    const int ps = mirror ? q : p, qs = mirror ? p : q;
+    const long long plane = (long long)m1 * m2, off = (long long)qs * m1 + ps;
+    double sx = 0;
+    int s = 0;
+    for (; s + 8 <= nsplit; s += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(s + u) * plane + off];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sx += v[u];
+    }
+    for (; s < nsplit; ++s) sx += part[s * plane + off];
+    C[(long long)q * ldc + p] = double2{alpha * sx, 0.0};
+}
+
 // Tiles of Q x Q blocks of 16 x 16 (k_gram80: Q = 5) on 2 Q waves.  Wave w computes the real
 // (w even) or imaginary (w odd) part of its blocks with one A fragment per block row:
 //   Re C = a^T b,  Im C = a'^T b  with a'[2k] = -Im A[k], a'[2k+1] = Re A[k],
@@ -446,19 +576,25 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
 // 8 columns: measured 14 % faster than two waves with 16-column chunks, whose staging
 // registers do not fit three waves.
 // ----------------------------------------------------------------------------------------
-template <int CB, int RA>
+// PAIR: the paired real form (every complex column of S and Y holds two real columns, real
+// part then imaginary part).  Cm then holds, for complex column l of S and j of Y, the real
+// 2 x 2 coefficient block as two double2 at Cm[j ldcm + 2 l] = (c00, c01) and
+// Cm[j ldcm + 2 l + 1] = (c10, c11) with c_uv the coefficient of real column 2 l + u of S in
+// real column 2 j + v of Y; Y.x += S.x c00 + S.y c10, Y.y += S.x c01 + S.y c11.
+template <int CB, int RA, bool PAIR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(long long K, SegList segs, long long lds, int m,
                                                 const double2* __restrict__ Cm, int ldcm, int nb, double beta,
                                                 const double2* Z, long long ldz, double2* Y, long long ldy) {
     // a workgroup owns RW = 64 RA rows (each wave 16 RA rows) and 16 CB columns; LDS chunks of
-    // UL columns of S and UL rows of Cm, the next chunk held in registers while the MFMAs of
-    // the current one run
+    // UL columns of S and UL rows of Cm (2 UL for the paired form), the next chunk held in
+    // registers while the MFMAs of the current one run
     constexpr int UL = 8;
     constexpr int NC = 16 * CB;
     constexpr int RW = 64 * RA;
     constexpr int SP = RW + 1;                       // row pitch of the S chunk (double2)
+    constexpr int CR = PAIR ? 2 * UL : UL;           // staged coefficient rows per chunk
     __shared__ double2 lsS[UL * SP];
-    __shared__ double2 lsC[UL * NC];
+    __shared__ double2 lsC[CR * NC];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const long long R0 = (long long)blockIdx.x * RW;
     const int j0 = blockIdx.y * NC;
@@ -470,7 +606,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
         for (int b = 0; b < CB; ++b) { accr[a][b] = d4{0, 0, 0, 0}; acci[a][b] = d4{0, 0, 0, 0}; }
     constexpr int SPASS = UL * RW / 256;
-    constexpr int CPASS = (UL * NC + 255) / 256;
+    constexpr int CPASS = (CR * NC + 255) / 256;
     double2 rs[SPASS], rc[CPASS];
     auto gload = [&](int l0) {
 #pragma unroll
@@ -483,9 +619,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
         for (int u = 0; u < CPASS; ++u) {
             const int idx = u * 256 + t;
-            const int l = idx % UL, j = idx / UL;
+            const int l = idx % CR, j = idx / CR;
             rc[u] = double2{0, 0};
-            if (idx < UL * NC && l0 + l < m && j0 + j < nb) rc[u] = Cm[(long long)(j0 + j) * ldcm + l0 + l];
+            const int lc = PAIR ? l0 + l / 2 : l0 + l;
+            const int row = PAIR ? 2 * l0 + l : l0 + l;
+            if (idx < CR * NC && lc < m && j0 + j < nb) rc[u] = Cm[(long long)(j0 + j) * ldcm + row];
         }
     };
     gload(0);
@@ -499,7 +637,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
         for (int u = 0; u < CPASS; ++u) {
             const int idx = u * 256 + t;
-            if (idx < UL * NC) lsC[(idx % UL) * NC + idx / UL] = rc[u];
+            if (idx < CR * NC) lsC[(idx % CR) * NC + idx / CR] = rc[u];
         }
         __syncthreads();
         if (l0 + UL < m) gload(l0 + UL);
@@ -509,9 +647,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             double2 sv[RA];
 #pragma unroll
             for (int a = 0; a < RA; ++a) sv[a] = lsS[l * SP + wr + 16 * a + ri];
-            double2 cv[CB];
+            double2 cv[CB], cw[CB];
 #pragma unroll
-            for (int b = 0; b < CB; ++b) cv[b] = lsC[l * NC + 16 * b + ri];
+            for (int b = 0; b < CB; ++b) {
+                if (PAIR) {
+                    cv[b] = lsC[(2 * l) * NC + 16 * b + ri];        // (c00, c01)
+                    cw[b] = lsC[(2 * l + 1) * NC + 16 * b + ri];    // (c10, c11)
+                } else {
+                    cv[b] = lsC[l * NC + 16 * b + ri];
+                    cw[b] = double2{-cv[b].y, cv[b].x};              // complex: (c10, c11) = (-Im, Re)
+                }
+            }
             // the four real products in rounds over all tiles, so that two MFMAs into one
             // accumulator are 2 RA CB MFMAs apart
 #pragma unroll
@@ -525,8 +671,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             for (int a = 0; a < RA; ++a)
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
-                    accr[a][b] = mfma(-sv[a].y, cv[b].y, accr[a][b]);
-                    acci[a][b] = mfma(sv[a].y, cv[b].x, acci[a][b]);
+                    accr[a][b] = mfma(sv[a].y, cw[b].x, accr[a][b]);
+                    acci[a][b] = mfma(sv[a].y, cw[b].y, acci[a][b]);
                 }
         }
     }
@@ -864,43 +1010,127 @@ __global__ void __launch_bounds__(RB) k_colnorm2_part(long long K, const double2
     }
 }
 
-// Residual norms of a block in one pass: for column j (omega_j = om[j]) the partial sums of
-// |HF - w G|^2, |HG - w F|^2, |F|^2, |G|^2 into part[((q * ncols) + j) * nchunk + chunk].
-__global__ void __launch_bounds__(RB) k_resnorm2_part(long long K, const double2* __restrict__ HF,
-                                                      const double2* __restrict__ G, const double2* __restrict__ HG,
-                                                      const double2* __restrict__ F, long long ld,
-                                                      const double* __restrict__ om, long long kper,
-                                                      double* __restrict__ part) {
-    __shared__ double red[4][RB / 64];
-    const int col = blockIdx.y, chunk = blockIdx.x, ncols = gridDim.y;
+// Paired real form: column reductions over the real columns 2 J + u (u = 0 real part, 1
+// imaginary part) of complex column J.
+// part[(2 J + u) * nchunk + chunk] = sum over the chunk of X_u[k, J]^2
+__global__ void __launch_bounds__(RB) k_colnorm2_pair_part(long long K, const double2* __restrict__ X, long long ldx,
+                                                           long long kper, double* __restrict__ part) {
+    __shared__ double red[2][RB / 64];
+    const int col = blockIdx.y, chunk = blockIdx.x;
+    const long long k0 = chunk * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const double2* x = X + (long long)col * ldx;
+    double s0 = 0, s1 = 0;
+    for (long long k = k0 + threadIdx.x; k < k1; k += RB) {
+        const double2 v = x[k];
+        s0 += v.x * v.x;
+        s1 += v.y * v.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_down(s0, off);
+        s1 += __shfl_down(s1, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double a = 0;
+        for (int w = 0; w < RB / 64; ++w) a += red[threadIdx.x][w];
+        part[(2LL * col + threadIdx.x) * gridDim.x + chunk] = a;
+    }
+}
+
+// Residual norms of the real columns j = 2 J + u (omega_j = om[j]): partial sums of
+// |HF_j - w G_j|^2, |HG_j - w F_j|^2, |F_j|^2, |G_j|^2 into part[((q * 2 ncols) + j) * nchunk + chunk]
+// (ncols complex columns).  Dot products f_j . g_j with q = 4 when dots != 0 (5 sums).
+__global__ void __launch_bounds__(RB) k_resnorm2_pair_part(long long K, const double2* __restrict__ HF,
+                                                           const double2* __restrict__ G,
+                                                           const double2* __restrict__ HG,
+                                                           const double2* __restrict__ F, long long ld,
+                                                           const double* __restrict__ om, long long kper,
+                                                           double* __restrict__ part) {
+    __shared__ double red[8][RB / 64];
+    const int col = blockIdx.y, chunk = blockIdx.x, nr = 2 * gridDim.y;
     const long long k0 = chunk * kper;
     long long k1 = k0 + kper;
     if (k1 > K) k1 = K;
     const long long off = (long long)col * ld;
-    const double w = om[col];
-    double s[4] = {0, 0, 0, 0};
+    const double w0 = om[2 * col], w1 = om[2 * col + 1];
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (long long k = k0 + threadIdx.x; k < k1; k += RB) {
         const double2 hf = HF[off + k], g = G[off + k], hg = HG[off + k], f = F[off + k];
-        const double a = hf.x - w * g.x, b = hf.y - w * g.y;
-        const double cc = hg.x - w * f.x, d = hg.y - w * f.y;
-        s[0] += a * a + b * b;
-        s[1] += cc * cc + d * d;
-        s[2] += f.x * f.x + f.y * f.y;
-        s[3] += g.x * g.x + g.y * g.y;
+        const double a0 = hf.x - w0 * g.x, a1 = hf.y - w1 * g.y;
+        const double b0 = hg.x - w0 * f.x, b1 = hg.y - w1 * f.y;
+        s[0] += a0 * a0;
+        s[1] += a1 * a1;
+        s[2] += b0 * b0;
+        s[3] += b1 * b1;
+        s[4] += f.x * f.x;
+        s[5] += f.y * f.y;
+        s[6] += g.x * g.x;
+        s[7] += g.y * g.y;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
         double v = s[q];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
         if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
-        const int q = threadIdx.x;
+    if (threadIdx.x < 8) {
+        const int q = threadIdx.x >> 1, u = threadIdx.x & 1;
         double a = 0;
-        for (int wv = 0; wv < RB / 64; ++wv) a += red[q][wv];
-        part[((long long)q * ncols + col) * gridDim.x + chunk] = a;
+        for (int wv = 0; wv < RB / 64; ++wv) a += red[threadIdx.x][wv];
+        part[((long long)q * nr + 2 * col + u) * gridDim.x + chunk] = a;
     }
+}
+
+// Dot products of the real columns: part[(2 J + u) * nchunk + chunk] = sum F_u[k, J] G_u[k, J]
+__global__ void __launch_bounds__(RB) k_dot_pair_part(long long K, const double2* __restrict__ F,
+                                                      const double2* __restrict__ G, long long ld, long long kper,
+                                                      double* __restrict__ part) {
+    __shared__ double red[2][RB / 64];
+    const int col = blockIdx.y, chunk = blockIdx.x;
+    const long long k0 = chunk * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const long long off = (long long)col * ld;
+    double s0 = 0, s1 = 0;
+    for (long long k = k0 + threadIdx.x; k < k1; k += RB) {
+        const double2 f = F[off + k], g = G[off + k];
+        s0 += f.x * g.x;
+        s1 += f.y * g.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_down(s0, o);
+        s1 += __shfl_down(s1, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double a = 0;
+        for (int w = 0; w < RB / 64; ++w) a += red[threadIdx.x][w];
+        part[(2LL * col + threadIdx.x) * gridDim.x + chunk] = a;
+    }
+}
+
+// Paired coefficient blocks: for complex columns l < mp of S and j < nbp of Y,
+// Cp[j ldp + 2 l] = (Cr[2 l, 2 j], Cr[2 l, 2 j + 1]), Cp[j ldp + 2 l + 1] = (Cr[2 l + 1, 2 j], Cr[2 l + 1, 2 j + 1])
+// with Cr[i, jj] = real part of C[jj ldc + r0 + i]; ldp = 2 mp
+__global__ void k_pack_pair_coef(int mp, int nbp, const double2* __restrict__ C, int ldc, int r0,
+                                 double2* __restrict__ Cp) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (l >= mp || j >= nbp) return;
+    const double2* c0 = C + (long long)(2 * j) * ldc + r0 + 2 * l;
+    const double2* c1 = C + (long long)(2 * j + 1) * ldc + r0 + 2 * l;
+    Cp[(long long)j * 2 * mp + 2 * l] = double2{c0[0].x, c1[0].x};
+    Cp[(long long)j * 2 * mp + 2 * l + 1] = double2{c0[1].x, c1[1].x};
 }
 
 __global__ void k_colnorm2_final(int ncols, int nchunk, const double* __restrict__ part, double* out) {
@@ -943,10 +1173,13 @@ static bool make_seglist(const Seg* segs, int nseg, SegList* sl, int* m) {
 
 // K-splits of a Gram launch: about 2048 workgroups, rounded to whole rounds of the
 // workgroups resident on the device at once (slots), so that the last round is not left
-// partly empty; at least 512 rows per split.  Returns the rows per split (a multiple of GKC).
-static long long gram_rows_per_split(long long K, long long items, long long slots, long long* nsplit) {
+// partly empty; at least 512 rows per split; at most max_split splits (0: no cap).
+// Returns the rows per split (a multiple of GKC).
+static long long gram_rows_per_split(long long K, long long items, long long slots, long long* nsplit,
+                                     long long max_split) {
     const long long rounds = std::max<long long>(1, (2048 + slots / 2) / slots);
     long long ns = std::max<long long>(1, std::min<long long>((K + 511) / 512, rounds * slots / items));
+    if (max_split > 0) ns = std::min(ns, max_split);
     long long kper = (K + ns - 1) / ns;
     kper = ((kper + GKC - 1) / GKC) * GKC;
     *nsplit = std::max<long long>(1, (K + kper - 1) / kper);
@@ -961,6 +1194,7 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         return ctx_fail(c, BDG_EINVAL, "gram: 1..4 segments");
     if (m1 <= 0 || m2 <= 0) return BDG_OK;
     if (hermitian && m1 != m2) return ctx_fail(c, BDG_EINVAL, "gram: Hermitian form needs m1 == m2");
+    const long long max_split = 0;
     // Tiling by measured cost (MI355X, 6.3 M rows): a 64-tile takes 0.204 ms per 16 x 16 block
     // it executes, an 80-tile 0.264 ms (the Hermitian diagonal tiles of either about as long
     // as a full tile), so 80-tiles win where they remove padding: m = 80 against 128, 80 x 240
@@ -975,7 +1209,7 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         const int ncg = (m2 + 63) / 64;
         long long nsplit = 1;
         // five resident workgroups per CU (five waves per SIMD)
-        const long long kper = gram_rows_per_split(K, ncg, 5LL * c->ncu, &nsplit);
+        const long long kper = gram_rows_per_split(K, ncg, 5LL * c->ncu, &nsplit, max_split);
         void* ws = nullptr;
         BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
         const long long total = nsplit * ncg;
@@ -994,7 +1228,7 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
     const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
     long long nsplit = 1;
     // resident workgroups per CU: k_gram three (three waves per SIMD), k_gram80 one
-    const long long kper = gram_rows_per_split(K, ntiles, (t80 ? 1LL : 3LL) * c->ncu, &nsplit);
+    const long long kper = gram_rows_per_split(K, ntiles, (t80 ? 1LL : 3LL) * c->ncu, &nsplit, max_split);
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
     // A == B (same segments, same stride): the diagonal tiles need one panel
@@ -1042,7 +1276,7 @@ bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long l
     constexpr int RA = 1;
     dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), (unsigned)ctiles);
 #define BDG_UPD(CBV) \
-    hipLaunchKernelGGL((k_update<CBV, RA>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy)
+    hipLaunchKernelGGL((k_update<CBV, RA, false>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy)
     switch (cb) {
         case 1: BDG_UPD(1); break;
         case 2: BDG_UPD(2); break;
@@ -1052,6 +1286,115 @@ bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long l
     }
 #undef BDG_UPD
     return hip_check(c, hipGetLastError(), "k_update");
+}
+
+bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long long lda, const Seg* sb, int nbs,
+                         long long ldb, double alpha, double2* C, int ldc, int hermitian) {
+    SegList A, B;
+    int m1 = 0, m2 = 0;
+    if (!make_seglist(sa, na, &A, &m1) || !make_seglist(sb, nbs, &B, &m2))
+        return ctx_fail(c, BDG_EINVAL, "gram: 1..4 segments");
+    if (m1 <= 0 || m2 <= 0) return BDG_OK;
+    if (hermitian && m1 != m2) return ctx_fail(c, BDG_EINVAL, "gram: symmetric form needs m1 == m2");
+    const long long r1 = 2LL * m1, r2 = 2LL * m2;
+    const long long max_split = 0;
+    const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
+    const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
+    long long nsplit = 1;
+    const long long kper = gram_rows_per_split(K, ntiles, 3LL * c->ncu, &nsplit, max_split);
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * r1 * r2 * sizeof(double), &ws));
+    bool same = hermitian && na == nbs && lda == ldb;
+    for (int i = 0; same && i < na; ++i) same = sa[i].p == sb[i].p && sa[i].ncols == sb[i].ncols;
+    const long long total = nsplit * ntiles;
+    const long long per_xcd = (total + 7) / 8;
+    const int h = hermitian ? 1 : 0, sm = same ? 1 : 0;
+    hipLaunchKernelGGL(k_gram_pair, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda, B, ldb,
+                       kper, tn, h, sm, ntiles, total, per_xcd, (double*)ws);
+    BDG_HIP(c, hipGetLastError());
+    const long long tot = r1 * r2;
+    hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, (int)r1,
+                       (int)r2, (int)nsplit, (const double*)ws, alpha, C, ldc, h);
+    return hip_check(c, hipGetLastError(), "k_gram_pair");
+}
+
+bdg_status update_pair(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cr, int ldcr,
+                       int r0, int nbr, double beta, const double2* Z, long long ldz, double2* Y, long long ldy) {
+    if (nbr <= 0 || K <= 0) return BDG_OK;
+    if (nbr & 1) return ctx_fail(c, BDG_EINVAL, "update_pair: odd real column count");
+    SegList sl;
+    int mp = 0;
+    if (!make_seglist(segs, nseg, &sl, &mp)) return ctx_fail(c, BDG_EINVAL, "update: 1..4 segments");
+    const int nbp = nbr / 2;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 7, (size_t)2 * mp * nbp * sizeof(double2), &ws));
+    double2* Cp = (double2*)ws;
+    hipLaunchKernelGGL(k_pack_pair_coef, dim3((unsigned)((mp + 127) / 128), (unsigned)nbp), dim3(128), 0, c->stream,
+                       mp, nbp, Cr, ldcr, r0, Cp);
+    BDG_HIP(c, hipGetLastError());
+    const int cb = std::min(5, (nbp + 15) / 16);
+    const int ctiles = (nbp + 16 * cb - 1) / (16 * cb);
+    constexpr int RA = 1;
+    dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), (unsigned)ctiles);
+#define BDG_UPDP(CBV) \
+    hipLaunchKernelGGL((k_update<CBV, RA, true>), grid, dim3(256), 0, c->stream, K, sl, lds, mp, (const double2*)Cp, \
+                       2 * mp, nbp, beta, Z, ldz, Y, ldy)
+    switch (cb) {
+        case 1: BDG_UPDP(1); break;
+        case 2: BDG_UPDP(2); break;
+        case 3: BDG_UPDP(3); break;
+        case 4: BDG_UPDP(4); break;
+        default: BDG_UPDP(5); break;
+    }
+#undef BDG_UPDP
+    return hip_check(c, hipGetLastError(), "k_update_pair");
+}
+
+bdg_status colnorm2_pair(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx, double* out_dev) {
+    if (ncols <= 0) return BDG_OK;
+    int nchunk = (int)std::min<long long>(256, (K + 8191) / 8192);
+    if (nchunk < 1) nchunk = 1;
+    const long long kper = (K + nchunk - 1) / nchunk;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 2, (size_t)2 * ncols * nchunk * sizeof(double), &ws));
+    hipLaunchKernelGGL(k_colnorm2_pair_part, dim3((unsigned)nchunk, (unsigned)ncols), dim3(RB), 0, c->stream, K, X,
+                       ldx, kper, (double*)ws);
+    BDG_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((2 * ncols + 127) / 128)), dim3(128), 0, c->stream,
+                       2 * ncols, nchunk, (const double*)ws, out_dev);
+    return hip_check(c, hipGetLastError(), "k_colnorm2_pair");
+}
+
+bdg_status resnorm2_pair(bdg_ctx* c, long long K, int ncols, const double2* HF, const double2* G, const double2* HG,
+                         const double2* F, long long ld, const double* om_dev, double* out_dev) {
+    if (ncols <= 0) return BDG_OK;
+    int nchunk = (int)std::min<long long>(128, (K + 8191) / 8192);
+    if (nchunk < 1) nchunk = 1;
+    const long long kper = (K + nchunk - 1) / nchunk;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 2, (size_t)8 * ncols * nchunk * sizeof(double), &ws));
+    hipLaunchKernelGGL(k_resnorm2_pair_part, dim3((unsigned)nchunk, (unsigned)ncols), dim3(RB), 0, c->stream, K, HF,
+                       G, HG, F, ld, om_dev, kper, (double*)ws);
+    BDG_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((8 * ncols + 127) / 128)), dim3(128), 0, c->stream,
+                       8 * ncols, nchunk, (const double*)ws, out_dev);
+    return hip_check(c, hipGetLastError(), "k_resnorm2_pair");
+}
+
+bdg_status dot_pair(bdg_ctx* c, long long K, int ncols, const double2* F, const double2* G, long long ld,
+                    double* out_dev) {
+    if (ncols <= 0) return BDG_OK;
+    int nchunk = (int)std::min<long long>(256, (K + 8191) / 8192);
+    if (nchunk < 1) nchunk = 1;
+    const long long kper = (K + nchunk - 1) / nchunk;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 2, (size_t)2 * ncols * nchunk * sizeof(double), &ws));
+    hipLaunchKernelGGL(k_dot_pair_part, dim3((unsigned)nchunk, (unsigned)ncols), dim3(RB), 0, c->stream, K, F, G, ld,
+                       kper, (double*)ws);
+    BDG_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((2 * ncols + 127) / 128)), dim3(128), 0, c->stream,
+                       2 * ncols, nchunk, (const double*)ws, out_dev);
+    return hip_check(c, hipGetLastError(), "k_dot_pair");
 }
 
 bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, double2 alpha, const double2* A,
@@ -1150,20 +1493,4 @@ bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long l
     hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((ncols + 127) / 128)), dim3(128), 0, c->stream, ncols,
                        nchunk, (const double*)ws, out_dev);
     return hip_check(c, hipGetLastError(), "k_colnorm2");
-}
-
-bdg_status resnorm2(bdg_ctx* c, long long K, int ncols, const double2* HF, const double2* G, const double2* HG,
-                    const double2* F, long long ld, const double* om_dev, double* out_dev) {
-    if (ncols <= 0) return BDG_OK;
-    int nchunk = (int)std::min<long long>(128, (K + 8191) / 8192);
-    if (nchunk < 1) nchunk = 1;
-    const long long kper = (K + nchunk - 1) / nchunk;
-    void* ws = nullptr;
-    BDG_TRY(ctx_scratch(c, 2, (size_t)4 * ncols * nchunk * sizeof(double), &ws));
-    hipLaunchKernelGGL(k_resnorm2_part, dim3((unsigned)nchunk, (unsigned)ncols), dim3(RB), 0, c->stream, K, HF, G, HG,
-                       F, ld, om_dev, kper, (double*)ws);
-    BDG_HIP(c, hipGetLastError());
-    hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((4 * ncols + 127) / 128)), dim3(128), 0, c->stream,
-                       4 * ncols, nchunk, (const double*)ws, out_dev);
-    return hip_check(c, hipGetLastError(), "k_resnorm2");
 }

@@ -28,6 +28,12 @@
 //              matrices and the coefficient rows.  With float64 images, H P is recomputed
 //              from P before each projection (the recurrence image of the short step P
 //              loses relative accuracy by the inverse convergence factor per iteration).
+// For a real ground state H_+ and H_- are real, so the eigenvectors can be taken real and the
+// iteration runs on real vectors, two to a complex column (paired form: real part and
+// imaginary part).  The FFT apply and the preconditioner act on both halves of a complex
+// column at once; Gram matrices and updates treat the halves as separate real columns, so a
+// block of b real vectors costs the MFMA work of b / 2 complex ones in both (a complex Gram of
+// m columns needs 4 m^2 real products per row, the real Gram of m columns m^2).
 // Gram matrices and updates run on the FP64 matrix cores; the projected problems on the
 // device in FP64; the host only reads back residual norms and small singular values.
 #include "common.h"
@@ -60,60 +66,12 @@ template <typename Fn> struct Defer {
 };
 template <typename Fn> Defer<Fn> defer(Fn fn) { return Defer<Fn>{fn}; }
 
-// Z(:, t) = X(:, idx[t]) - w[idx[t]] Y(:, idx[t]) for t < gridDim.y (active columns)
-__global__ void k_cols_axmy_idx(long long K, const double2* __restrict__ X, const double2* __restrict__ Y, long long ld,
-                                const double* __restrict__ w, const int* __restrict__ idx, double2* __restrict__ Z,
-                                long long ldz) {
-    const int t = blockIdx.y;
-    const long long j = idx[t];
-    const double s = w[j];
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
-        double2 a = X[j * ld + i], b = Y[j * ld + i];
-        Z[t * ldz + i] = cmk<double2>(a.x - s * b.x, a.y - s * b.y);
-    }
-}
-
-// scales of the basis columns [F (nb), W, P]: 1 for F, 1 / ||column|| after it (0 for a
-// zero column); v holds the squared norms from position nb on
-__global__ void k_make_scales(int m, int nb, double* v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    if (i < nb) {
-        v[i] = 1.0;
-    } else {
-        const double a = v[i];
-        v[i] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
-    }
-}
-
-// A(i, j) *= sl[i] * sr[j] (m x m, ld lda)
-__global__ void k_small_scale2(int m, double2* A, int lda, const double* __restrict__ sl, const double* __restrict__ sr) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-    if (i >= m) return;
-    const double f = sl[i] * sr[j];
-    double2 a = A[(long long)j * lda + i];
-    A[(long long)j * lda + i] = cmk<double2>(a.x * f, a.y * f);
-}
-
-// A(i, j) *= s[i] (m x n, ld lda)
-__global__ void k_small_scale_rows(int m, double2* A, int lda, const double* __restrict__ s) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-    if (i >= m) return;
-    double2 a = A[(long long)j * lda + i];
-    A[(long long)j * lda + i] = cmk<double2>(a.x * s[i], a.y * s[i]);
-}
-
-// the same in float32 output (the mixed form's correction block)
-__global__ void k_cols_axmy_idx32(long long K, const double2* __restrict__ X, const double2* __restrict__ Y,
-                                  long long ld, const double* __restrict__ w, const int* __restrict__ idx,
-                                  float2* __restrict__ Z, long long ldz) {
-    const int t = blockIdx.y;
-    const long long j = idx[t];
-    const double s = w[j];
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
-        double2 a = X[j * ld + i], b = Y[j * ld + i];
-        Z[t * ldz + i] = cmk<float2>((float)(a.x - s * b.x), (float)(a.y - s * b.y));
-    }
+// A(p, q) = A(q, p) for r0 <= p < m, q = blockIdx.y < r0: the first r0 rows of a symmetric
+// m x m matrix (ld lda) copied into its first r0 columns below them
+__global__ void k_small_mirror_rows(int m, int r0, double2* A, int lda) {
+    const int p = r0 + blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
+    if (p >= m) return;
+    A[(long long)q * lda + p] = A[(long long)p * lda + q];
 }
 
 // Y(:, t) = X(:, idx[t]) for t < gridDim.y; X and Y must not overlap
@@ -243,15 +201,109 @@ __global__ void k_small_copy(int rows, int cols, const double2* __restrict__ A, 
         B[(long long)j * ldb + i] = A[(long long)j * lda + i];
 }
 
-// u = f + g, v = f - g for ncols columns (half columns of stride nh) into interleaved vectors
-__global__ void k_make_uv(long long nh, int ncols, const double2* __restrict__ F, const double2* __restrict__ G,
-                          const double* __restrict__ scale, double2* __restrict__ UV) {
+// A(:, j) = 0 for j0 <= j < cols
+__global__ void k_small_zero_cols(int rows, int j0, double2* A, int lda) {
+    const int j = j0 + blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x)
+        A[(long long)j * lda + i] = double2{0.0, 0.0};
+}
+
+// ---------------------------------------------------------------------------------------
+// Paired real form (real ground states): the operator is real, so the iteration runs on real
+// trial vectors, two to a complex column (real column 2 J = real part of complex column J,
+// 2 J + 1 = its imaginary part).  The FFT apply acts on both at once (H (a + i b) = H a + i H b
+// for real H); the Gram matrices and updates take the parts as separate real columns.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double pget(const double2* X, long long ld, int j, long long i) {
+    const double2 v = X[(long long)(j >> 1) * ld + i];
+    return (j & 1) ? v.y : v.x;
+}
+
+// 1 / sqrt(sq) (0 for sq <= 0): the unit-column factor from a squared norm
+__device__ __forceinline__ double unit_scale(double sq) { return sq > 0.0 ? 1.0 / sqrt(sq) : 0.0; }
+
+// complex output column T of Z holds real columns 2 T, 2 T + 1:
+// Z_r(t) = (X_r(j) - w[j] Y_r(j)) / sqrt(sq[j]) with j = idx[t], t < 2 gridDim.y; sq holds the
+// squared norms of those differences, so every output column has unit norm.  Two real vectors
+// share one complex FFT downstream, whose rounding is relative to the larger of the pair: a
+// column kept at its raw (possibly tiny) scale would take the rounding of its partner.
+__global__ void k_pair_axmy_idx(long long K, const double2* __restrict__ X, const double2* __restrict__ Y, long long ld,
+                                const double* __restrict__ w, const int* __restrict__ idx,
+                                const double* __restrict__ sq, double2* __restrict__ Z, long long ldz) {
+    const int T = blockIdx.y;
+    const int j0 = idx[2 * T], j1 = idx[2 * T + 1];
+    const double s0 = w[j0], s1 = w[j1];
+    const double c0 = unit_scale(sq[j0]), c1 = unit_scale(sq[j1]);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x)
+        Z[T * ldz + i] = cmk<double2>(c0 * (pget(X, ld, j0, i) - s0 * pget(Y, ld, j0, i)),
+                                      c1 * (pget(X, ld, j1, i) - s1 * pget(Y, ld, j1, i)));
+}
+
+// the same in float32 output (the mixed form's correction block)
+__global__ void k_pair_axmy_idx32(long long K, const double2* __restrict__ X, const double2* __restrict__ Y,
+                                  long long ld, const double* __restrict__ w, const int* __restrict__ idx,
+                                  const double* __restrict__ sq, float2* __restrict__ Z, long long ldz) {
+    const int T = blockIdx.y;
+    const int j0 = idx[2 * T], j1 = idx[2 * T + 1];
+    const double s0 = w[j0], s1 = w[j1];
+    const double c0 = unit_scale(sq[j0]), c1 = unit_scale(sq[j1]);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x)
+        Z[T * ldz + i] = cmk<float2>((float)(c0 * (pget(X, ld, j0, i) - s0 * pget(Y, ld, j0, i))),
+                                     (float)(c1 * (pget(X, ld, j1, i) - s1 * pget(Y, ld, j1, i))));
+}
+
+// X_r(t) *= 1 / sqrt(sq[t]) for the 2 gridDim.y real columns of gridDim.y complex columns
+__global__ void k_pair_unit_cols(long long K, double2* __restrict__ X, long long ld, const double* __restrict__ sq) {
+    const int T = blockIdx.y;
+    const double c0 = unit_scale(sq[2 * T]), c1 = unit_scale(sq[2 * T + 1]);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        const double2 v = X[T * ld + i];
+        X[T * ld + i] = cmk<double2>(c0 * v.x, c1 * v.y);
+    }
+}
+
+// Y_r(t) = X_r(idx[t]) for t < 2 gridDim.y; X and Y must not overlap
+__global__ void k_pair_gather(long long K, const double2* __restrict__ X, long long ldx, const int* __restrict__ idx,
+                              double2* __restrict__ Y, long long ldy) {
+    const int T = blockIdx.y;
+    const int j0 = idx[2 * T], j1 = idx[2 * T + 1];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x)
+        Y[T * ldy + i] = cmk<double2>(pget(X, ldx, j0, i), pget(X, ldx, j1, i));
+}
+
+// real start columns from a complex start block in (f, g) form (vector j at X0 + 2 j nh):
+// real column j = real part plus imaginary part of vector j, for j < nvec
+__global__ void k_pair_start(long long nh, int nvec, const double2* __restrict__ X0, double2* __restrict__ F,
+                             double2* __restrict__ G) {
+    const int T = blockIdx.y;
+    const int j0 = 2 * T, j1 = 2 * T + 1;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (long long)gridDim.x * blockDim.x) {
+        double2 f = F[T * nh + i], g = G[T * nh + i];
+        if (j0 < nvec) {
+            const double2 a = X0[(long long)j0 * 2 * nh + i], b = X0[(long long)j0 * 2 * nh + nh + i];
+            f.x = a.x + a.y;
+            g.x = b.x + b.y;
+        }
+        if (j1 < nvec) {
+            const double2 a = X0[(long long)j1 * 2 * nh + i], b = X0[(long long)j1 * 2 * nh + nh + i];
+            f.y = a.x + a.y;
+            g.y = b.x + b.y;
+        }
+        F[T * nh + i] = f;
+        G[T * nh + i] = g;
+    }
+}
+
+// (u, v) = scale_j (f_j + g_j, f_j - g_j) for the real columns j < ncols, written as complex
+// vectors with zero imaginary parts
+__global__ void k_pair_make_uv(long long nh, int ncols, const double2* __restrict__ F, const double2* __restrict__ G,
+                               const double* __restrict__ scale, double2* __restrict__ UV) {
     const int j = blockIdx.y;
     const double s = scale[j];
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (long long)gridDim.x * blockDim.x) {
-        double2 f = F[j * nh + i], g = G[j * nh + i];
-        UV[j * 2 * nh + i] = cmk<double2>(s * (f.x + g.x), s * (f.y + g.y));
-        UV[j * 2 * nh + nh + i] = cmk<double2>(s * (f.x - g.x), s * (f.y - g.y));
+        const double f = pget(F, nh, j, i), g = pget(G, nh, j, i);
+        UV[j * 2 * nh + i] = cmk<double2>(s * (f + g), 0.0);
+        UV[j * 2 * nh + nh + i] = cmk<double2>(s * (f - g), 0.0);
     }
 }
 
@@ -624,50 +676,73 @@ bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double null_tol) 
 // =====================================================================================
 // bdg_biortho
 // =====================================================================================
+namespace {
+
+// Factors of the bi-orthogonalization: B = h^d G^H F = U diag(s) V^H, C_f = V s^-1/2 into
+// w.buf[1], C_g = U s^-1/2 into w.buf[2] (nvec x nvec, ld nvec; columns with
+// s_j <= 1e-12 s_1 dropped and set to zero).  s_host: nvec values; *rank: the columns kept.
+// Workspace from ctx_alloc / ctx_scratch.
+bdg_status biortho_factors(bdg_ctx* c, Small& w, int nvec, const double2* F, const double2* G, double* s_host,
+                           int* rank) {
+    const long long nh = 3 * c->npts;
+    BDG_TRY(small_alloc(c, w, nvec));
+    double2* B = w.buf[0];
+    double2* V = w.buf[1];
+    double2* Cg = w.buf[2];
+    BDG_TRY(gram<double2, double2>(c, nh, nvec, nvec, G, nh, F, nh, c->hd, B, nvec, 0));
+    BDG_TRY(small_svd(c, nvec, nvec, B, nvec, V, nvec, w.s[0]));
+    BDG_TRY(d2h(c, s_host, w.s[0], nvec * sizeof(double)));
+    int r = 0;
+    while (r < nvec && s_host[r] > 1e-12 * s_host[0] && s_host[r] > 0) ++r;
+    // C_f = V s^-1/2 ; C_g = (U s) s^-3/2 ; dropped columns -> 0
+    BDG_TRY(small_colpow(c, nvec, nvec, V, nvec, w.s[0], -0.5));
+    BDG_TRY(small_copy(c, nvec, nvec, B, nvec, Cg, nvec));
+    BDG_TRY(small_colpow(c, nvec, nvec, Cg, nvec, w.s[0], -1.5));
+    if (r < nvec) {
+        hipLaunchKernelGGL(k_small_zero_cols, dim3((unsigned)((nvec + 255) / 256), (unsigned)(nvec - r)), dim3(256),
+                           0, c->stream, nvec, r, V, nvec);
+        hipLaunchKernelGGL(k_small_zero_cols, dim3((unsigned)((nvec + 255) / 256), (unsigned)(nvec - r)), dim3(256),
+                           0, c->stream, nvec, r, Cg, nvec);
+        BDG_HIP(c, hipGetLastError());
+    }
+    *rank = r;
+    return BDG_OK;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+    const char* p = (const char*)a;
+    const char* q = (const char*)b;
+    return p < q + bytes && q < p + bytes;
+}
+
+}  // namespace
+
 extern "C" bdg_status bdg_biortho(bdg_ctx* c, int nvec, void* F_dev, void* G_dev, double* sigma, int* rank) {
     if (!c) return BDG_EINVAL;
     if (nvec <= 0 || nvec > 512 || !F_dev || !G_dev) return ctx_fail(c, BDG_EINVAL, "bdg_biortho: bad arguments");
     const long long nh = 3 * c->npts;
-    Small w;
-    bdg_status st = small_alloc(c, w, nvec);
-    if (st != BDG_OK) { small_free(c, w); return st; }
+    const size_t bytes = (size_t)nvec * nh * sizeof(double2);
     double2* F = (double2*)F_dev;
     double2* G = (double2*)G_dev;
+    Small w;
     double2* tmp = nullptr;
-    st = ctx_alloc(c, (void**)&tmp, (size_t)nvec * nh * sizeof(double2));
-    auto run = [&]() -> bdg_status {
-        double2* B = w.buf[0];
-        double2* V = w.buf[1];
-        double2* Cg = w.buf[2];
-        BDG_TRY(gram<double2, double2>(c, nh, nvec, nvec, G, nh, F, nh, c->hd, B, nvec, 0));
-        BDG_TRY(small_svd(c, nvec, nvec, B, nvec, V, nvec, w.s[0]));
-        std::vector<double> s(nvec);
-        BDG_TRY(d2h(c, s.data(), w.s[0], nvec * sizeof(double)));
-        int r = 0;
-        while (r < nvec && s[r] > 1e-12 * s[0] && s[r] > 0) ++r;
-        // C_f = V s^-1/2 ; C_g = (U s) s^-3/2 ; dropped columns -> 0
-        BDG_TRY(small_colpow(c, nvec, nvec, V, nvec, w.s[0], -0.5));
-        BDG_TRY(small_copy(c, nvec, nvec, B, nvec, Cg, nvec));
-        BDG_TRY(small_colpow(c, nvec, nvec, Cg, nvec, w.s[0], -1.5));
-        if (r < nvec) {
-            std::vector<double2> z((size_t)nvec * (nvec - r), cmk<double2>(0, 0));
-            BDG_TRY(h2d(c, V + (size_t)r * nvec, z.data(), z.size() * sizeof(double2)));
-            BDG_TRY(h2d(c, Cg + (size_t)r * nvec, z.data(), z.size() * sizeof(double2)));
-        }
-        Seg sf{F, nvec}, sg{G, nvec};
-        BDG_TRY(update(c, nh, &sf, 1, nh, V, nvec, nvec, 0.0, tmp, nh));
-        BDG_HIP(c, hipMemcpyAsync(F, tmp, (size_t)nvec * nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
-        BDG_TRY(update(c, nh, &sg, 1, nh, Cg, nvec, nvec, 0.0, tmp, nh));
-        BDG_HIP(c, hipMemcpyAsync(G, tmp, (size_t)nvec * nh * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
-        BDG_HIP(c, hipStreamSynchronize(c->stream));
-        if (sigma) std::memcpy(sigma, s.data(), nvec * sizeof(double));
-        if (rank) *rank = r;
-        return BDG_OK;
-    };
-    if (st == BDG_OK) st = run();
-    ctx_free(c, tmp);
-    small_free(c, w);
-    return st;
+    auto release = defer([&] {
+        ctx_free(c, tmp);
+        small_free(c, w);
+    });
+    std::vector<double> s(nvec);
+    int r = 0;
+    BDG_TRY(biortho_factors(c, w, nvec, F, G, s.data(), &r));
+    BDG_TRY(ctx_alloc(c, (void**)&tmp, bytes));
+    Seg sf{F, nvec}, sg{G, nvec};
+    BDG_TRY(update(c, nh, &sf, 1, nh, w.buf[1], nvec, nvec, 0.0, tmp, nh));
+    BDG_HIP(c, hipMemcpyAsync(F, tmp, bytes, hipMemcpyDeviceToDevice, c->stream));
+    BDG_TRY(update(c, nh, &sg, 1, nh, w.buf[2], nvec, nvec, 0.0, tmp, nh));
+    BDG_HIP(c, hipMemcpyAsync(G, tmp, bytes, hipMemcpyDeviceToDevice, c->stream));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    if (sigma) std::memcpy(sigma, s.data(), nvec * sizeof(double));
+    if (rank) *rank = r;
+    return BDG_OK;
 }
 
 // =====================================================================================
@@ -679,9 +754,10 @@ struct EigsOpts {
     double rtol = 1e-12;        // pivoted-Cholesky cut-off (Schur complement of the scaled Gram)
     double eps = 1e-10;         // LU pivot cut-off of the pairing matrix
     double null_tol = 1e-6;     // nullspace candidate test
-    double refresh_tol = 1e-3;  // mixed precision: float64 corrections from this residual on (the
-                                // float32 image floor eps32 ||H|| / omega is ~1e-3 for 3-D traps)
     int refresh_every = 25;     // float64 re-projection and image refresh period (iterations)
+    int refresh_every32 = 10;   // the same while W and P are applied in float32: F's recurrence
+                                // images then gather float32 rounding in proportion to the steps
+                                // taken since the last refresh
     int stall_iters = 10;       // mixed form: switch to float64 applies after this many
                                 // iterations without halving the residual, or at once when
                                 // it grows past rise_factor times its best value
@@ -715,11 +791,15 @@ bdg_status operator_bound(bdg_ctx* c, double* out) {
     return BDG_OK;
 }
 
-bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const void* X0_dev,
+bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, const void* X0_dev,
                      unsigned long long seed, double* omega_out, void* UV_dev, double* res_out, int* iters_out) {
     const EigsOpts opt;
     const long long npts = c->npts, nh = 3 * npts;
     const bool mixed = c->prob.precision == BDG_FP32_APPLY;
+    // real trial vectors in the paired form: nb real columns (the block rounded up to even)
+    // in nbc complex columns
+    const int nb = nb_req + (nb_req & 1);
+    const int nbc = nb / 2;
     const int m = 3 * nb;
     auto t_start = std::chrono::steady_clock::now();
     for (double& s : c->stats) s = 0;
@@ -750,18 +830,19 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     });
     BDG_TRY(small_alloc(c, w, std::max(m, 8)));
     S.nh = nh;
-    S.nb = nb;
-    for (int a = 0; a < 4; ++a) BDG_TRY(ctx_alloc(c, (void**)&S.arr[a], 4 * (size_t)nb * nh * sizeof(double2)));
+    S.nb = nbc;
+    for (int a = 0; a < 4; ++a) BDG_TRY(ctx_alloc(c, (void**)&S.arr[a], 4 * (size_t)nbc * nh * sizeof(double2)));
     if (mixed) {
-        BDG_TRY(ctx_alloc(c, (void**)&w32, 2 * (size_t)nb * nh * sizeof(float2)));
-        BDG_TRY(ctx_alloc(c, (void**)&y32, 2 * (size_t)nb * nh * sizeof(float2)));
+        // float32 staging of [W, P] (f halves, then g halves) and of their images
+        BDG_TRY(ctx_alloc(c, (void**)&w32, 4 * (size_t)nbc * nh * sizeof(float2)));
+        BDG_TRY(ctx_alloc(c, (void**)&y32, 4 * (size_t)nbc * nh * sizeof(float2)));
     }
     BDG_TRY(ctx_alloc(c, (void**)&acoef, (size_t)m * nb * sizeof(double2)));
     BDG_TRY(ctx_alloc(c, (void**)&bcoef, (size_t)m * nb * sizeof(double2)));
     BDG_TRY(ctx_alloc(c, (void**)&dvec, 8 * (size_t)nb * sizeof(double)));
     BDG_TRY(ctx_alloc(c, (void**)&d_act, (size_t)nb * sizeof(int)));
     BDG_TRY(ctx_alloc(c, (void**)&d_scl, 2 * (size_t)m * sizeof(double)));
-    double* d_sf = d_scl;          // column scales of S_f = [F, W_f, P_f]
+    double* d_sf = d_scl;          // squared column norms of S_f = [F, W_f, P_f] (W, P part)
     double* d_sg = d_scl + m;      // and of S_g
     double* d_om = dvec;
     double* d_n = dvec + nb;      // 4 nb norms
@@ -775,19 +856,19 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     S.slotF = 0; S.slotW = 1; S.slotP = -1; S.slotFree = 2; S.slotFree2 = 3;
     double2* F = S.col(SF, S.slotF);
     double2* G = S.col(SG, S.slotF);
-    if (X0_dev) {
-        BDG_HIP(c, hipMemcpy2DAsync(F, nh * sizeof(double2), X0_dev, 2 * nh * sizeof(double2), nh * sizeof(double2), nb,
-                                    hipMemcpyDeviceToDevice, c->stream));
-        BDG_HIP(c, hipMemcpy2DAsync(G, nh * sizeof(double2), (const double2*)X0_dev + nh, 2 * nh * sizeof(double2),
-                                    nh * sizeof(double2), nb, hipMemcpyDeviceToDevice, c->stream));
-    } else {
-        hipLaunchKernelGGL(k_randn, dim3(2048), dim3(256), 0, c->stream, (long long)nb * nh, seed, F);
-        hipLaunchKernelGGL(k_randn, dim3(2048), dim3(256), 0, c->stream, (long long)nb * nh, seed ^ 0x5851F42D4C957F2DULL, G);
-    }
-    BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, F, nb));
-    BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, G, nb));
+    // real start vectors: normals from `seed` (each complex normal gives two), then, with a start
+    // block, real column j = Re + Im of its vector j (a generic real direction of the vector's
+    // span; the operator is real, so its eigenvectors may be taken real)
+    hipLaunchKernelGGL(k_randn, dim3(2048), dim3(256), 0, c->stream, (long long)nbc * nh, seed, F);
+    hipLaunchKernelGGL(k_randn, dim3(2048), dim3(256), 0, c->stream, (long long)nbc * nh, seed ^ 0x5851F42D4C957F2DULL, G);
+    if (X0_dev)
+        hipLaunchKernelGGL(k_pair_start, grid_cols(nh, nbc), dim3(256), 0, c->stream, nh, nb_req,
+                           (const double2*)X0_dev, F, G);
+    BDG_HIP(c, hipGetLastError());
+    BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, F, nbc));
+    BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, G, nbc));
     double napply64 = 0, napply32 = 0;
-    BDG_TRY(apply64(c, nb, F, G, nh, S.col(HSF, S.slotF), S.col(HSG, S.slotF)));
+    BDG_TRY(apply64(c, nbc, F, G, nh, S.col(HSF, S.slotF), S.col(HSG, S.slotF)));
     napply64 += nb;
     double2* Gf = w.buf[0];
     double2* Gg = w.buf[1];
@@ -797,38 +878,60 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     std::vector<double> om;
     // per-column target: tol, or the rounding floor of the relative residual when that is larger
     auto target = [&](int j) { return std::max(tol, opt.floor_c * DBL_EPSILON * hbound / std::fabs(om[j])); };
-    auto grams = [&](const Seg* sf, const Seg* sg, const Seg* hf, const Seg* hg, int ns, int ldc) -> bdg_status {
-        BDG_TRY(gram_seg(c, nh, sf, ns, nh, sf, ns, nh, c->hd, Gf, ldc, 1));
-        BDG_TRY(gram_seg(c, nh, sg, ns, nh, sg, ns, nh, c->hd, Gg, ldc, 1));
-        BDG_TRY(gram_seg(c, nh, sg, ns, nh, sf, ns, nh, c->hd, Br, ldc, 0));
-        BDG_TRY(gram_seg(c, nh, sf, ns, nh, hf, ns, nh, c->hd, Mr, ldc, 1));
-        BDG_TRY(gram_seg(c, nh, sg, ns, nh, hg, ns, nh, c->hd, Kr, ldc, 1));
-        return BDG_OK;
+    // Gram matrices of S_f = [F, W_f, P_f], S_g = [G, W_g, P_g] and their images.  With
+    // cross_from_f the first block row of the projected operators is taken as (H F)^T S
+    // instead of F^T (H S): the images of W and P then enter only the [W, P] x [W, P] block.
+    // (Used while W and P are applied in float32: their images carry eps32 ||H|| whatever
+    // the residual, and in the F x [W, P] blocks that error would couple the converged
+    // directions to the corrections and stall the residual near eps32 ||H|| / omega; the
+    // images of F follow by recurrence and carry an error that falls with the step.)
+    auto grams = [&](const Seg* sf, const Seg* sg, const Seg* hf, const Seg* hg, int ns, int ldc,
+                     bool cross_from_f) -> bdg_status {
+        BDG_TRY(gram_seg_pair(c, nh, sf, ns, nh, sf, ns, nh, c->hd, Gf, ldc, 1));
+        BDG_TRY(gram_seg_pair(c, nh, sg, ns, nh, sg, ns, nh, c->hd, Gg, ldc, 1));
+        BDG_TRY(gram_seg_pair(c, nh, sg, ns, nh, sf, ns, nh, c->hd, Br, ldc, 0));
+        if (!cross_from_f) {
+            BDG_TRY(gram_seg_pair(c, nh, sf, ns, nh, hf, ns, nh, c->hd, Mr, ldc, 1));
+            BDG_TRY(gram_seg_pair(c, nh, sg, ns, nh, hg, ns, nh, c->hd, Kr, ldc, 1));
+            return BDG_OK;
+        }
+        const int r0 = 2 * sf[0].ncols;       // real columns of F
+        const size_t d = (size_t)r0 * ldc + r0;
+        BDG_TRY(gram_seg_pair(c, nh, hf, 1, nh, sf, ns, nh, c->hd, Mr, ldc, 0));
+        BDG_TRY(gram_seg_pair(c, nh, sf + 1, ns - 1, nh, hf + 1, ns - 1, nh, c->hd, Mr + d, ldc, 1));
+        BDG_TRY(gram_seg_pair(c, nh, hg, 1, nh, sg, ns, nh, c->hd, Kr, ldc, 0));
+        BDG_TRY(gram_seg_pair(c, nh, sg + 1, ns - 1, nh, hg + 1, ns - 1, nh, c->hd, Kr + d, ldc, 1));
+        const dim3 gm((unsigned)((ldc - r0 + 127) / 128), (unsigned)r0);
+        hipLaunchKernelGGL(k_small_mirror_rows, gm, dim3(128), 0, c->stream, ldc, r0, Mr, ldc);
+        hipLaunchKernelGGL(k_small_mirror_rows, gm, dim3(128), 0, c->stream, ldc, r0, Kr, ldc);
+        return hip_check(c, hipGetLastError(), "k_small_mirror_rows");
     };
-    // re-deflate F, G (and P) and recompute their images with float64 applies
-    auto refresh = [&](double2* F_, double2* G_, double2* HF_, double2* HG_) -> bdg_status {
-        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, F_, nb));
-        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, G_, nb));
-        BDG_TRY(apply64(c, nb, F_, G_, nh, HF_, HG_));
+    // re-deflate F, G (and P) and recompute their images with float64 applies; with_p = false
+    // leaves P alone (its images are recomputed from P in the same iteration anyway)
+    auto refresh = [&](double2* F_, double2* G_, double2* HF_, double2* HG_, bool with_p = true) -> bdg_status {
+        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, F_, nbc));
+        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, G_, nbc));
+        BDG_TRY(apply64(c, nbc, F_, G_, nh, HF_, HG_));
         napply64 += nb;
-        if (S.slotP >= 0) {
+        if (with_p && S.slotP >= 0) {
             double2* Pf = S.col(SF, S.slotP);
             double2* Pg = S.col(SG, S.slotP);
-            BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Pf, nb));
-            BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Pg, nb));
-            BDG_TRY(apply64(c, nb, Pf, Pg, nh, S.col(HSF, S.slotP), S.col(HSG, S.slotP)));
+            BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Pf, nbc));
+            BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Pg, nbc));
+            BDG_TRY(apply64(c, nbc, Pf, Pg, nh, S.col(HSF, S.slotP), S.col(HSG, S.slotP)));
             napply64 += nb;
         }
         return BDG_OK;
     };
     {
-        Seg sf{F, nb}, sg{G, nb}, hf{S.col(HSF, S.slotF), nb}, hg{S.col(HSG, S.slotF), nb};
-        BDG_TRY(grams(&sf, &sg, &hf, &hg, 1, nb));
+        Seg sf{F, nbc}, sg{G, nbc}, hf{S.col(HSF, S.slotF), nbc}, hg{S.col(HSG, S.slotF), nbc};
+        BDG_TRY(grams(&sf, &sg, &hf, &hg, 1, nb, false));
         BDG_TRY(rayleigh_ritz(c, w, nb, nb, Gf, Gg, Br, Mr, Kr, acoef, bcoef, om, opt.rtol, opt.eps));
         const int s_new = S.slotW;
         for (int a = 0; a < 4; ++a) {
-            Seg src{S.col(a, S.slotF), nb};
-            BDG_TRY(update(c, nh, &src, 1, nh, (a == SF || a == HSF) ? acoef : bcoef, nb, nb, 0.0, S.col(a, s_new), nh));
+            Seg src{S.col(a, S.slotF), nbc};
+            BDG_TRY(update_pair(c, nh, &src, 1, nh, (a == SF || a == HSF) ? acoef : bcoef, nb, 0, nb, 0.0,
+                                S.col(a, s_new), nh, S.col(a, s_new), nh));
         }
         S.slotW = S.slotF;
         S.slotF = s_new;
@@ -865,7 +968,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         auto t0 = now();
         // residual norms of every column in one pass over F, G and their images
         BDG_TRY(h2d(c, d_om, om.data(), nb * sizeof(double)));
-        BDG_TRY(resnorm2(c, nh, nb, HF, G, HG, F, nh, d_om, d_n));
+        BDG_TRY(resnorm2_pair(c, nh, nbc, HF, G, HG, F, nh, d_om, d_n));
         BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
         double rmax = 0;
         bool all_k = true;
@@ -876,30 +979,47 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             if (j < k) { rmax = std::max(rmax, res[j]); all_k = all_k && done; }
             if (!done) act.push_back(j);      // soft locking: converged columns get no correction
         }
+        if (act.size() & 1) {
+            // corrections go two to a complex column: add the converged column with the largest
+            // residual (nb is even, so one exists)
+            int jb = -1;
+            for (int j = 0; j < nb; ++j)
+                if (std::find(act.begin(), act.end(), j) == act.end() && (jb < 0 || res[j] > res[jb])) jb = j;
+            act.push_back(jb);
+        }
         const int nact = (int)act.size();
+        const int nactc = nact / 2;
         if (!(rmax == rmax)) return ctx_fail(c, BDG_EBREAKDOWN, "non-finite residual");
         if (debug_on())
             fprintf(stderr, "[bdg it %d] omega0=%.12f omega_k=%.12f res_max(k)=%.3e res0=%.3e active=%d\n", it, om[0],
                     om[k - 1], rmax, res[0], nact);
-        // mixed form: float32 applies of the correction block until the residual reaches
-        // refresh_tol or stops decreasing (the float32 rounding of the images sets a floor
-        // near eps32 ||H|| / omega, which can lie far above refresh_tol); then float64
-        // applies finish the solve
+        // mixed form: W and P are applied in float32 (their images carry relative rounding
+        // eps32 in every iteration) and F's images follow by recurrence, refreshed in float64
+        // every refresh_every32 iterations, so the rounding they gather is proportional to
+        // the steps taken since and falls with the residual.  Should the residual still stop
+        // falling (10 iterations without halving) or rise 4x above its best, float64 applies
+        // finish the solve.
         if (mixed && !force64) {
             // both detectors are armed once the start-up transient is over (residual < 0.1)
             if (!armed && rmax < 0.1) { armed = true; best_r = rmax; best_it = it; }
             if (armed) {
                 if (rmax < best_r * 0.5) { best_r = rmax; best_it = it; }
-                if (rmax <= opt.refresh_tol || it - best_it > opt.stall_iters || rmax > opt.rise_factor * best_r)
+                if (it - best_it > opt.stall_iters || rmax > opt.rise_factor * best_r) {
                     switch64 = true;
+                    if (debug_on())
+                        fprintf(stderr, "[bdg it %d] float64 applies from here: residual %.3e, best %.3e at it %d\n",
+                                it, rmax, best_r, best_it);
+                }
             }
         }
-        const bool want_refresh = switch64 || (it - last_refresh >= opt.refresh_every);
+        const bool phase32 = mixed && !force64;
+        const bool want_refresh =
+            switch64 || (it - last_refresh >= (phase32 ? opt.refresh_every32 : opt.refresh_every));
         if (want_refresh) {
             // re-project the basis off the generalized nullspace and recompute its images in
             // float64 (bounds the drift of the recurrence-updated images; in the mixed form
             // it also removes the float32 rounding the images carry)
-            BDG_TRY(refresh(F, G, HF, HG));
+            BDG_TRY(refresh(F, G, HF, HG, !(phase32 && !switch64)));
             if (switch64) { force64 = true; refreshed = true; switch64 = false; }
             last_refresh = it;
             --it;
@@ -909,9 +1029,9 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             // certify with a float64 apply of the current block
             double2* CF = S.col(HSF, S.slotFree);
             double2* CG = S.col(HSG, S.slotFree);
-            BDG_TRY(apply64(c, nb, F, G, nh, CF, CG));
+            BDG_TRY(apply64(c, nbc, F, G, nh, CF, CG));
             napply64 += nb;
-            BDG_TRY(resnorm2(c, nh, nb, CF, G, CG, F, nh, d_om, d_n));
+            BDG_TRY(resnorm2_pair(c, nh, nbc, CF, G, CG, F, nh, d_om, d_n));
             BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
             bool certified = true;
             for (int j = 0; j < nb; ++j) {
@@ -935,69 +1055,105 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         // mixed form writes the residuals in float32 and gets float64 back from the
         // preconditioner's last pass)
         BDG_TRY(h2d(c, d_act, act.data(), nact * sizeof(int)));
+        // residual directions scaled to unit columns (their squared norms are in d_n: q = 0
+        // for H_+ f - w g, q = 1 for H_- g - w f)
         if (mixed) {
-            hipLaunchKernelGGL(k_cols_axmy_idx32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HF,
-                               (const double2*)G, nh, (const double*)d_om, (const int*)d_act, w32, nh);
-            hipLaunchKernelGGL(k_cols_axmy_idx32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HG,
-                               (const double2*)F, nh, (const double*)d_om, (const int*)d_act,
-                               w32 + (size_t)nact * nh, nh);
+            hipLaunchKernelGGL(k_pair_axmy_idx32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh,
+                               (const double2*)HF, (const double2*)G, nh, (const double*)d_om, (const int*)d_act,
+                               (const double*)d_n, w32, nh);
+            hipLaunchKernelGGL(k_pair_axmy_idx32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh,
+                               (const double2*)HG, (const double2*)F, nh, (const double*)d_om, (const int*)d_act,
+                               (const double*)(d_n + nb), w32 + (size_t)nactc * nh, nh);
             BDG_HIP(c, hipGetLastError());
-            BlockRef<float2> x32{w32, w32 + (size_t)nact * nh, nh};
+            BlockRef<float2> x32{w32, w32 + (size_t)nactc * nh, nh};
             BlockRef<double2> y64{Wf, Wg, nh};
-            BDG_TRY(launch_precond_mixed(c, nact, x32, y64));
+            BDG_TRY(launch_precond_mixed(c, nactc, x32, y64));
         } else {
-            hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HF,
-                               (const double2*)G, nh, (const double*)d_om, (const int*)d_act, Wf, nh);
-            hipLaunchKernelGGL(k_cols_axmy_idx, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, (const double2*)HG,
-                               (const double2*)F, nh, (const double*)d_om, (const int*)d_act, Wg, nh);
+            hipLaunchKernelGGL(k_pair_axmy_idx, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, (const double2*)HF,
+                               (const double2*)G, nh, (const double*)d_om, (const int*)d_act, (const double*)d_n, Wf,
+                               nh);
+            hipLaunchKernelGGL(k_pair_axmy_idx, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, (const double2*)HG,
+                               (const double2*)F, nh, (const double*)d_om, (const int*)d_act,
+                               (const double*)(d_n + nb), Wg, nh);
             BDG_HIP(c, hipGetLastError());
-            BDG_TRY(launch_precond<double>(c, 3 * nact, 3, nh, Wf, Wf));
-            BDG_TRY(launch_precond<double>(c, 3 * nact, 3, nh, Wg, Wg));
+            BDG_TRY(launch_precond<double>(c, 3 * nactc, 3, nh, Wf, Wf));
+            BDG_TRY(launch_precond<double>(c, 3 * nactc, 3, nh, Wg, Wg));
         }
-        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Wf, nact));
-        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nact));
-        // W and P keep their raw scale in memory; unit columns are applied to the Gram
-        // matrices and to the coefficient rows instead (H (S diag(s)) = (H S) diag(s))
-        BDG_TRY(colnorm2(c, nh, nact, Wf, nh, d_sf + nb));
-        BDG_TRY(colnorm2(c, nh, nact, Wg, nh, d_sg + nb));
+        BDG_TRY(project_out(c, w, nh, D.Nm, D.pm, Wf, nactc));
+        BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nactc));
+        // W and P are scaled to unit columns in memory before they are applied: two real
+        // vectors share a complex FFT, whose rounding is relative to the larger of the pair
+        // (see k_pair_axmy_idx); the Gram matrices are then those of unit columns
+        BDG_TRY(colnorm2_pair(c, nh, nactc, Wf, nh, d_sf + nb));
+        BDG_TRY(colnorm2_pair(c, nh, nactc, Wg, nh, d_sg + nb));
+        hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, Wf, nh,
+                           (const double*)(d_sf + nb));
+        hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, Wg, nh,
+                           (const double*)(d_sg + nb));
         // P of the active columns only: gather them (and their images) into the free slot
         if (S.slotP >= 0 && nact < nb) {
             for (int a = 0; a < 4; ++a)
-                hipLaunchKernelGGL(k_cols_gather, grid_cols(nh, nact), dim3(256), 0, c->stream, nh,
+                hipLaunchKernelGGL(k_pair_gather, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh,
                                    (const double2*)S.col(a, S.slotP), nh, (const int*)d_act, S.col(a, S.slotFree),
                                    nh);
             BDG_HIP(c, hipGetLastError());
             std::swap(S.slotP, S.slotFree);
         }
+        const int np = S.slotP >= 0 ? nact : 0;
+        if (np) {
+            BDG_TRY(colnorm2_pair(c, nh, np / 2, S.col(SF, S.slotP), nh, d_sf + nb + nact));
+            BDG_TRY(colnorm2_pair(c, nh, np / 2, S.col(SG, S.slotP), nh, d_sg + nb + nact));
+            hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, np / 2), dim3(256), 0, c->stream, nh,
+                               S.col(SF, S.slotP), nh, (const double*)(d_sf + nb + nact));
+            hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, np / 2), dim3(256), 0, c->stream, nh,
+                               S.col(SG, S.slotP), nh, (const double*)(d_sg + nb + nact));
+        }
+        BDG_HIP(c, hipGetLastError());
         BDG_TRY(sync_if());
         t_prec += ms_since(t0);
         auto t1 = now();
         double2* HWf = S.col(HSF, S.slotW);
         double2* HWg = S.col(HSG, S.slotW);
-        if (mixed && !force64) {
-            float2* wf32 = w32;
-            float2* wg32 = w32 + (size_t)nact * nh;
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wf, nh,
-                               wf32, nh);
-            hipLaunchKernelGGL(k_to32, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const double2*)Wg, nh,
-                               wg32, nh);
-            BlockRef<const float2> X{wf32, wg32, nh};
-            BlockRef<float2> Y{y32, y32 + (size_t)nact * nh, nh};   // lo: H_- W_g, hi: H_+ W_f
-            BDG_TRY(launch_apply<float>(c, BDG_FORM_FG, 0, nact, X, Y));
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact, (const float2*)y32, nh,
-                               HWg, nh);
-            hipLaunchKernelGGL(k_to64, grid_cols(nh, nact), dim3(256), 0, c->stream, nh, nact,
-                               (const float2*)(y32 + (size_t)nact * nh), nh, HWf, nh);
-            napply32 += nact;
+        const bool w32img = mixed && !force64;
+        if (w32img) {
+            // W and P (when present) in one float32 launch: f halves [W_f, P_f], g halves
+            // [W_g, P_g]; P's images are recomputed from P as in the float64 form below
+            const int nv = S.slotP >= 0 ? 2 * nactc : nactc;
+            float2* f32 = w32;
+            float2* g32 = w32 + (size_t)nv * nh;
+            const double2* src_f[2] = {Wf, S.slotP >= 0 ? S.col(SF, S.slotP) : nullptr};
+            const double2* src_g[2] = {Wg, S.slotP >= 0 ? S.col(SG, S.slotP) : nullptr};
+            double2* dst_hf[2] = {HWf, S.slotP >= 0 ? S.col(HSF, S.slotP) : nullptr};
+            double2* dst_hg[2] = {HWg, S.slotP >= 0 ? S.col(HSG, S.slotP) : nullptr};
+            const int nparts = S.slotP >= 0 ? 2 : 1;
+            for (int q = 0; q < nparts; ++q) {
+                hipLaunchKernelGGL(k_to32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc, src_f[q], nh,
+                                   f32 + (size_t)q * nactc * nh, nh);
+                hipLaunchKernelGGL(k_to32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc, src_g[q], nh,
+                                   g32 + (size_t)q * nactc * nh, nh);
+            }
+            BDG_HIP(c, hipGetLastError());
+            BlockRef<const float2> X{f32, g32, nh};
+            BlockRef<float2> Y{y32, y32 + (size_t)nv * nh, nh};   // lo: H_- [W_g, P_g], hi: H_+ [W_f, P_f]
+            BDG_TRY(launch_apply<float>(c, BDG_FORM_FG, 0, nv, X, Y));
+            for (int q = 0; q < nparts; ++q) {
+                hipLaunchKernelGGL(k_to64, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc,
+                                   (const float2*)(y32 + (size_t)q * nactc * nh), nh, dst_hg[q], nh);
+                hipLaunchKernelGGL(k_to64, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc,
+                                   (const float2*)(y32 + (size_t)(nv + q * nactc) * nh), nh, dst_hf[q], nh);
+            }
+            BDG_HIP(c, hipGetLastError());
+            napply32 += 2 * nv;
         } else {
-            BDG_TRY(apply64(c, nact, Wf, Wg, nh, HWf, HWg));
+            BDG_TRY(apply64(c, nactc, Wf, Wg, nh, HWf, HWg));
             napply64 += nact;
         }
-        // with float64 images, P's images are recomputed from P: the recurrence [H W, H P] a
-        // carries the cancellation in P = [W, P] a (a short step built from unit columns) into
-        // the images, whose relative error then grows by the convergence factor per iteration
+        // P's images are recomputed from P (in float32 above, in float64 here): the recurrence
+        // [H W, H P] a carries the cancellation in P = [W, P] a (a short step built from unit
+        // columns) into the images, whose relative error then grows by the convergence factor
+        // per iteration
         if (S.slotP >= 0 && !(mixed && !force64)) {
-            BDG_TRY(apply64(c, nact, S.col(SF, S.slotP), S.col(SG, S.slotP), nh, S.col(HSF, S.slotP),
+            BDG_TRY(apply64(c, nactc, S.col(SF, S.slotP), S.col(SG, S.slotP), nh, S.col(HSF, S.slotP),
                             S.col(HSG, S.slotP)));
             napply64 += nact;
         }
@@ -1005,35 +1161,14 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         t_apply += ms_since(t1);
         auto t2 = now();
         // Gram matrices of [F, W, P] (W and P: active columns)
-        const int np = S.slotP >= 0 ? nact : 0;
         const int ns = np > 0 ? 3 : 2;
         const int mc = nb + nact + np;
-        Seg sf[3] = {{F, nb}, {Wf, nact}, {np ? S.col(SF, S.slotP) : nullptr, np}};
-        Seg sg[3] = {{G, nb}, {Wg, nact}, {np ? S.col(SG, S.slotP) : nullptr, np}};
-        Seg hf[3] = {{HF, nb}, {HWf, nact}, {np ? S.col(HSF, S.slotP) : nullptr, np}};
-        Seg hg[3] = {{HG, nb}, {HWg, nact}, {np ? S.col(HSG, S.slotP) : nullptr, np}};
-        BDG_TRY(grams(sf, sg, hf, hg, ns, mc));
-        if (np) {
-            BDG_TRY(colnorm2(c, nh, np, S.col(SF, S.slotP), nh, d_sf + nb + nact));
-            BDG_TRY(colnorm2(c, nh, np, S.col(SG, S.slotP), nh, d_sg + nb + nact));
-        }
-        {
-            const dim3 g1((unsigned)((mc + 127) / 128));
-            hipLaunchKernelGGL(k_make_scales, g1, dim3(128), 0, c->stream, mc, nb, d_sf);
-            hipLaunchKernelGGL(k_make_scales, g1, dim3(128), 0, c->stream, mc, nb, d_sg);
-            const dim3 g2((unsigned)((mc + 127) / 128), (unsigned)mc);
-            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Gf, mc, (const double*)d_sf,
-                               (const double*)d_sf);
-            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Gg, mc, (const double*)d_sg,
-                               (const double*)d_sg);
-            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Br, mc, (const double*)d_sg,
-                               (const double*)d_sf);
-            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Mr, mc, (const double*)d_sf,
-                               (const double*)d_sf);
-            hipLaunchKernelGGL(k_small_scale2, g2, dim3(128), 0, c->stream, mc, Kr, mc, (const double*)d_sg,
-                               (const double*)d_sg);
-            BDG_HIP(c, hipGetLastError());
-        }
+        const int npc = np / 2;
+        Seg sf[3] = {{F, nbc}, {Wf, nactc}, {npc ? S.col(SF, S.slotP) : nullptr, npc}};
+        Seg sg[3] = {{G, nbc}, {Wg, nactc}, {npc ? S.col(SG, S.slotP) : nullptr, npc}};
+        Seg hf[3] = {{HF, nbc}, {HWf, nactc}, {npc ? S.col(HSF, S.slotP) : nullptr, npc}};
+        Seg hg[3] = {{HG, nbc}, {HWg, nactc}, {npc ? S.col(HSG, S.slotP) : nullptr, npc}};
+        BDG_TRY(grams(sf, sg, hf, hg, ns, mc, w32img));
         BDG_TRY(sync_if());
         t_gram += ms_since(t2);
         auto t3 = now();
@@ -1053,13 +1188,6 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
             continue;
         }
         if (rst != BDG_OK) { final_status = rst; break; }
-        {
-            // coefficients of the raw (unscaled) columns
-            const dim3 g2((unsigned)((mc + 127) / 128), (unsigned)nb);
-            hipLaunchKernelGGL(k_small_scale_rows, g2, dim3(128), 0, c->stream, mc, acoef, mc, (const double*)d_sf);
-            hipLaunchKernelGGL(k_small_scale_rows, g2, dim3(128), 0, c->stream, mc, bcoef, mc, (const double*)d_sg);
-            BDG_HIP(c, hipGetLastError());
-        }
         t_small += ms_since(t3);
         auto t4 = now();
         // updates: P_new = [W, P] a[nb:] into the free slot, then F_new = F a[:nb] + P_new
@@ -1068,12 +1196,13 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
         for (int a = 0; a < 4; ++a) {
             const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
             const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
-            BDG_TRY(update(c, nh, seg + 1, ns - 1, nh, coef + nb, mc, nb, 0.0, S.col(a, dst_P), nh));
+            BDG_TRY(update_pair(c, nh, seg + 1, ns - 1, nh, coef, mc, nb, nb, 0.0, S.col(a, dst_P), nh,
+                                S.col(a, dst_P), nh));
         }
         for (int a = 0; a < 4; ++a) {
             const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
             const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
-            BDG_TRY(update_add(c, nh, seg, 1, nh, coef, mc, nb, 1.0, S.col(a, dst_P), nh, S.col(a, dst_F), nh));
+            BDG_TRY(update_pair(c, nh, seg, 1, nh, coef, mc, 0, nb, 1.0, S.col(a, dst_P), nh, S.col(a, dst_F), nh));
         }
         // rotate slot roles
         const int oldF = S.slotF, oldP = S.slotP;
@@ -1095,16 +1224,17 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb, double tol, int max_iter, const 
     if (iters_out) *iters_out = std::min(it, max_iter);
     if (UV_dev) {
         // exact <f, g> = 1/4 through one real scale per column
-        BDG_TRY(gram<double2, double2>(c, nh, kk, kk, G, nh, F, nh, c->hd, w.buf[0], kk, 0));
-        std::vector<double2> fg((size_t)kk * kk);
-        BDG_TRY(d2h(c, fg.data(), w.buf[0], fg.size() * sizeof(double2)));
+        const int kkc = (kk + 1) / 2;
+        BDG_TRY(dot_pair(c, nh, kkc, F, G, nh, d_n));
+        std::vector<double> fg(2 * kkc);
+        BDG_TRY(d2h(c, fg.data(), d_n, fg.size() * sizeof(double)));
         std::vector<double> scl(kk);
         for (int j = 0; j < kk; ++j) {
-            const double v = fg[(size_t)j * kk + j].x;
+            const double v = c->hd * fg[j];
             scl[j] = v > 0 ? 1.0 / std::sqrt(4.0 * v) : 0.0;
         }
         BDG_TRY(h2d(c, d_n, scl.data(), kk * sizeof(double)));
-        hipLaunchKernelGGL(k_make_uv, grid_cols(nh, kk), dim3(256), 0, c->stream, nh, kk, (const double2*)F,
+        hipLaunchKernelGGL(k_pair_make_uv, grid_cols(nh, kk), dim3(256), 0, c->stream, nh, kk, (const double2*)F,
                            (const double2*)G, (const double*)d_n, (double2*)UV_dev);
         BDG_HIP(c, hipGetLastError());
     }

@@ -166,3 +166,62 @@ def test_complete_pivoting_lu_biorthogonalizes(p, q, rank):
     cg = Cg.cpu().numpy().reshape(-1)[:p * rank].reshape(rank, p).T
     assert np.abs(cg.conj().T @ B @ cf - np.eye(rank)).max() < 1e-8
     ctx.close()
+
+
+# Paired real form: A, B hold two real columns per complex column (real part, imaginary part);
+# sym: 0 general, 1 B = A, 2 B = D A (the Rayleigh-Ritz shape S^T (H S) with symmetric H);
+# shapes reach single and several tiles, K-splits and ragged tails.
+@pytest.mark.parametrize("K,m1,m2,sym", [(37, 5, 7, 0), (3072, 64, 64, 1), (20000, 120, 120, 2), (100000, 120, 120, 1),
+                                         (5000, 40, 120, 0), (12, 65, 65, 1), (70001, 3, 16, 0), (9000, 36, 36, 2)])
+def test_gram_pair_matches_numpy(K, m1, m2, sym):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"gram pair K={K} {m1}x{m2} sym={sym}")
+    ctx = _ctx()
+    A = W.random_block((m1, K), seed=1)
+    if sym == 1:
+        B = A
+    elif sym == 2:
+        B = A * np.random.default_rng(3).uniform(0.5, 2.0, K)[None, :]
+    else:
+        B = W.random_block((m2, K), seed=2)
+    Ad = torch.from_numpy(A).cuda()
+    Bd = Ad if sym == 1 else torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    C = torch.zeros((2 * m2, 2 * m1), dtype=torch.complex128, device="cuda")   # column-major 2 m1 x 2 m2
+    st = ctx._lib.bdg_test_gram_pair(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 0.5, _p(C), 2 * m1, 1 if sym else 0)
+    assert st == _lib.BDG_OK
+    got = C.cpu().numpy().T
+    # real columns: 2 p + u is the real (u = 0) or imaginary (u = 1) part of complex column p
+    Ar = np.stack([A.real, A.imag], axis=1).reshape(2 * m1, K)
+    Br = np.stack([B.real, B.imag], axis=1).reshape(2 * m2, K)
+    ref = 0.5 * (Ar @ Br.T)
+    assert np.all(got.imag == 0.0)
+    err = np.abs(got.real - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("K,m,nb,beta", [(37, 5, 4, 0.0), (1000, 20, 16, 0.0), (5000, 120, 80, 1.0),
+                                         (129, 7, 34, -0.5), (100000, 12, 8, 0.0)])
+def test_update_pair_matches_numpy(K, m, nb, beta):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"update pair K={K} m={m} nb={nb}")
+    ctx = _ctx()
+    S = W.random_block((m, K), seed=3)
+    Cr = np.random.default_rng(4).standard_normal((nb, 2 * m))     # column-major 2 m x nb, real
+    Y0 = W.random_block((nb // 2, K), seed=5)
+    Sd, Yd = torch.from_numpy(S).cuda(), torch.from_numpy(Y0).cuda()
+    Cd = torch.from_numpy((Cr + 0.0j).astype(np.complex128)).cuda()
+    st = ctx._lib.bdg_test_update_pair(ctx._h, K, m, _p(Sd), K, _p(Cd), 2 * m, nb, beta, _p(Yd), K)
+    assert st == _lib.BDG_OK
+    got = Yd.cpu().numpy()
+    Sr = np.stack([S.real, S.imag], axis=1).reshape(2 * m, K)
+    Yr0 = np.stack([Y0.real, Y0.imag], axis=1).reshape(nb, K)
+    ref = Cr @ Sr + beta * Yr0                                   # rows: real output columns
+    got_r = np.stack([got.real, got.imag], axis=1).reshape(nb, K)
+    err = np.abs(got_r - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 1e-13
+    ctx.close()

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import bdg, branch, lrep
+from oracle import bdg, branch, lrep, scalar
 from tests.gpu_util import make_ctx, oracle_ground, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -87,12 +87,20 @@ def test_2d_eigs_match_oracle_and_branch(kind):
     ctx.close()
 
 
-def test_mixed_precision_eigs_agree_with_fp64():
+def test_mixed_precision_eigs_agree_with_fp64_and_oracles():
+    """3-D 16^3 trap: the FP64 solve within 1e-9 and the float32-apply solve within 1e-6 of
+    the six-component oracle iteration and of the scalar branch oracle; the two GPU forms
+    agree with each other."""
     torch = torch_cuda()
     from paper_2506_08308_amd import Precision
     w = W.Workload("3d_16_fm", 3, (16, 16, 16), (5.0, 5.0, 5.0), "harmonic3_z2", 40.0, -1.0, 0.1, k=8, block=12)
     say("eigs mixed", w.name)
     V, r, coef = oracle_ground(w)
+    out_o, _, _, _ = lrep.solve(coef, r.phi, w.n, w.L, w.k, W.start_block(w), 1e-10, V=V, mu=r.mu)
+    M = w.magnetization
+    phi = np.tensordot(np.array([(1 + M) / 2, np.sqrt((1 - M * M) / 2), (1 - M) / 2]), r.phi, axes=1)
+    bs = scalar.fm_branches(phi, r.mu[0], V, w.beta_n, w.beta_s, w.n, w.L, {"density": 6, "magnon": 8, "gapped": 8},
+                            tol=1e-10, k_total=w.k)
     res = {}
     for prec in (Precision.FP64, Precision.FP32_APPLY):
         ctx = make_ctx(w, prec, V)
@@ -102,6 +110,10 @@ def test_mixed_precision_eigs_agree_with_fp64():
         res[prec] = out
         ctx.close()
     a, b = np.array(res[Precision.FP64]["omega"]), np.array(res[Precision.FP32_APPLY]["omega"])
+    for ref in (out_o.omega, bs.omega):
+        say("   rel err fp64", np.abs(a / ref - 1).max(), "mixed", np.abs(b / ref - 1).max())
+        assert np.allclose(a, ref, rtol=1e-9)
+        assert np.allclose(b, ref, rtol=1e-6)
     assert np.allclose(a, b, rtol=1e-6)
     assert max(res[Precision.FP32_APPLY]["residual"]) <= 1e-8
     # the x and y Kohn modes omega = gamma = 1 of the (1, 1, 2) trap (Analytical eigenpairs

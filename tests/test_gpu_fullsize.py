@@ -1,14 +1,20 @@
 """Full-size parity: the GPU path at the target grids, in the configuration bench.py times.
 
+Two oracles supply the stored spectra in tests/golden (each written by a committed script
+that calls only oracle/): the six-component subspace iteration (make_golden.py) and the
+matrix-free scalar branch decomposition of the single-mode and polar ground states
+(make_branch_golden.py; Section 2.3), an independent formulation.
+
 * 2-D 256 x 256 trap (k = 32, block 48, residual 1e-8, FP64), beta_s = -2 and +2: every
-  frequency against the oracle's own full-size solve stored in tests/golden (written by
-  tests/golden/make_golden.py from oracle/ alone), relative error <= 1e-9.
-* 3-D 128^3 trap (k = 64, block 80, residual 1e-8, float32-apply mixed precision):
-  properties that hold at any size -- the Kohn (centre-of-mass) modes at the trap
-  frequencies 1, 1, 2 (exact for a harmonic trap), residuals <= 1e-8 re-measured with an
-  independent FP64 context, bi-orthogonality <f_i, g_j> = delta_ij / 4, and the single-mode
-  structure of the ferromagnetic ground state.
-* The uniform state on the same 128^3 grid: the Bogoliubov dispersion closed form.
+  frequency against both oracles, relative error <= 1e-9.
+* 3-D 128^3 trap (k = 64, block 80, residual 1e-8): all 64 frequencies against the branch
+  oracle, relative error <= 1e-9 for the FP64 solve and <= 1e-6 for the float32-apply mixed
+  solve; for the mixed solve also the Kohn (centre-of-mass) modes at the trap frequencies
+  1, 1, 2, residuals <= 1e-8 re-measured with an independent FP64 context,
+  bi-orthogonality <f_i, g_j> = delta_ij / 4, and the single-mode ground state.
+* The same 3-D trap on the 64^3 grid in both precisions: all 64 frequencies against the
+  branch oracle and the 16 lowest against the six-component oracle.
+* The uniform state on the 128^3 grid: the Bogoliubov dispersion closed form.
 """
 import json
 import os
@@ -37,7 +43,57 @@ def test_c2_full_size_matches_oracle(w):
     out = ctx.eigs(w.k, w.block, tol=w.tol, X0=torch.from_numpy(W.start_block(w)).to("cuda"), want_vectors=False)
     om = np.array(out["omega"])
     rel = np.abs(om - np.array(ref["omega"])) / np.array(ref["omega"])
-    say(f"   {out['iters']} iterations, max rel err {rel.max():.2e}")
+    say(f"   {out['iters']} iterations, max rel err {rel.max():.2e} (six-component oracle)")
+    assert rel.max() <= 1e-9
+    rel_b = _branch_errors(om, w.name)
+    say(f"   max rel err {rel_b.max():.2e} (branch oracle)")
+    assert rel_b.max() <= 1e-9
+    ctx.close()
+
+
+def _branch_golden(name):
+    with open(os.path.join(GOLDEN, f"{name}_branch_omega.json")) as f:
+        return json.load(f)
+
+
+def _branch_errors(om, name, k=None):
+    ref = np.array(_branch_golden(name)["omega"])
+    k = len(om) if k is None else k
+    return np.abs(np.asarray(om)[:k] - ref[:k]) / ref[:k]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_apply"])
+def test_c3_physics_64_matches_both_oracles(prec):
+    """The 3-D trap on the 64^3 grid (k = 64, block 80, residual 1e-8): all 64 frequencies
+    against the branch oracle, the 16 lowest against the six-component oracle."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Precision
+    w = W.scaled(W.C3, 64).with_(precision=prec)
+    say("64^3", w.name, prec)
+    ctx = make_ctx(w)
+    ctx.ground_state(tol=w.gs_tol)
+    out = ctx.eigs(w.k, w.block, tol=w.tol, X0=torch.from_numpy(W.start_block(w)).to("cuda"), want_vectors=False)
+    om = np.array(out["omega"])
+    bound = 1e-9 if prec == "fp64" else 1e-6
+    rel_b = _branch_errors(om, "3d_n64_fm")
+    with open(os.path.join(GOLDEN, "3d_n64_fm_lrep_omega.json")) as f:
+        lr = np.array(json.load(f)["omega"])
+    rel_l = np.abs(om[:len(lr)] - lr) / lr
+    say(f"   {out['iters']} iterations; max rel err {rel_b.max():.2e} (branch), {rel_l.max():.2e} (six-component)")
+    assert rel_b.max() <= bound
+    assert rel_l.max() <= bound
+    ctx.close()
+
+
+def test_c3_full_size_fp64_matches_branch_oracle():
+    torch = torch_cuda()
+    w = W.C3_FP64
+    say("full size", w.name)
+    ctx = make_ctx(w)
+    ctx.ground_state(tol=w.gs_tol)
+    out = ctx.eigs(w.k, w.block, tol=w.tol, X0=torch.from_numpy(W.start_block(w)).to("cuda"), want_vectors=False)
+    rel = _branch_errors(out["omega"], "3d_n128_fm")
+    say(f"   {out['iters']} iterations, max rel err {rel.max():.2e} over {len(rel)} (branch oracle)")
     assert rel.max() <= 1e-9
     ctx.close()
 
@@ -59,6 +115,10 @@ def test_c3_full_size_properties():
     out = ctx.eigs(w.k, w.block, tol=w.tol, X0=torch.from_numpy(W.start_block(w)).to("cuda"))
     om = np.array(out["omega"])
     say(f"   {out['iters']} iterations; omega {np.round(om, 8).tolist()}")
+    # all 64 against the branch oracle (mixed precision: <= 1e-6)
+    rel = _branch_errors(om, "3d_n128_fm")
+    say(f"   max rel err {rel.max():.2e} over {len(rel)} (branch oracle)")
+    assert rel.max() <= 1e-6
     # Kohn modes at the trap frequencies (gamma_x, gamma_y, gamma_z) = (1, 1, 2)
     assert np.sum(np.abs(om - 1.0) <= 1e-7) >= 2
     assert np.sum(np.abs(om - 2.0) <= 2e-7) >= 1
@@ -72,7 +132,9 @@ def test_c3_full_size_properties():
         y = ctx64.apply(x, Form.UV)
         res.append(float(torch.linalg.vector_norm(y - om[j] * x) / (om[j] * torch.linalg.vector_norm(x))))
     say(f"   max residual (FP64 re-apply) {max(res):.2e}")
-    assert max(res) <= 1.5e-8
+    # the library certifies res <= tol = 1e-8 with its own float64 apply; 1 % covers the
+    # rounding of this re-measurement (relative rounding of a residual ~ eps ||H|| / omega)
+    assert max(res) <= 1.01e-8
     # bi-orthogonality of the (f, g) halves: <f_i, g_j> = delta_ij / 4 away from degeneracies
     f = 0.5 * (uv[:, :3] + uv[:, 3:])
     g = 0.5 * (uv[:, :3] - uv[:, 3:])
@@ -91,7 +153,10 @@ def test_uniform_state_full_grid_matches_dispersion():
     torch = torch_cuda()
     from paper_2506_08308_amd import Precision
     n, L, bn, bs = (128, 128, 128), (8.0, 8.0, 8.0), 400.0, -4.0
-    w = W.Workload("3d_n128_uniform_fm", 3, n, L, "zero", bn, bs, 0.0, k=19, block=24, tol=1e-10)
+    # block 32: the iteration runs on real vectors, and the next shell of the closed form is
+    # 12-fold degenerate (a complex block of 24 spans cos and sin of a shell with one vector
+    # each; a real block needs room for both)
+    w = W.Workload("3d_n128_uniform_fm", 3, n, L, "zero", bn, bs, 0.0, k=19, block=32, tol=1e-10)
     say("uniform", w.name)
     ref = branch.uniform_spectrum(n, L, bn, bs, "fm", 20)
     assert ref[19] > ref[18] * (1 + 1e-3)

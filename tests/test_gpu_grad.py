@@ -23,12 +23,16 @@ def _cluster_mean(vals, omega, tol=1e-8):
     return out
 
 
-@pytest.mark.parametrize("case", ["1d", "2d"])
+@pytest.mark.parametrize("case", ["1d", "2d", "2d64"])
 def test_gradient_matches_oracle(case):
     torch = torch_cuda()
     from paper_2506_08308_amd import Precision
     if case == "1d":
         w = W.Workload("1d_64_fm", 1, (64,), (8.0,), "harmonic1", 10.0, -0.5, 0.2, k=6, block=8)
+    elif case == "2d64":
+        # the gradient configuration's lattice trap and interactions on the 64^2 grid; k = 6
+        # ends at a gap (omega_7 / omega_6 = 1.09)
+        w = W.Workload("2d_64_grad_fm", 2, (64, 64), (12.0, 12.0), "lattice2", 100.0, -2.0, 0.0, k=6, block=10)
     else:
         # k = 7 keeps the degenerate pair omega_6 = omega_7 whole (x <-> y symmetry); a cut
         # through a degenerate eigenspace makes the gradient of its members basis dependent

@@ -75,3 +75,46 @@ def test_perturbed_density_edges():
         ctx.perturbed_density([1.0], uv, float("nan"), [0.0])
     assert e.value.status == _lib.BDG_EINVAL
     ctx.close()
+
+
+@pytest.mark.parametrize("w,k,block", [
+    (W.C1, 8, 8),
+    (W.Workload("2d_64x32_aniso_fm", 2, (64, 32), (8.0, 6.0), "harmonic2_aniso", 40.0, -1.0, 0.0), 10, 14),
+    (W.Workload("3d_32_z2_fm", 3, (32, 32, 32), (6.0, 6.0, 6.0), "harmonic3_z2", 40.0, -1.0, 0.1), 10, 16),
+], ids=lambda x: getattr(x, "name", str(x)))
+def test_mode_amplitudes_match_oracle(w, k, block):
+    """bdg_mode_amplitudes on eigenvectors and on arbitrary fields against oracle.modes."""
+    torch = torch_cuda()
+    say("mode amplitudes", w.name)
+    ctx, phi, out = _solve(w, k, block)
+    X = torch.from_numpy(W.random_block((2, 6) + w.shape, seed=5)).to("cuda")
+    for uv in (out["uv"], X):
+        got = np.array(ctx.mode_amplitudes(uv))
+        ref = modes.mode_amplitudes(uv.cpu().numpy(), w.n, w.L)
+        assert got.shape == ref.shape
+        assert np.allclose(got[..., :2], ref[..., :2], rtol=1e-13, atol=0)
+        assert np.abs(got[..., 2:] - ref[..., 2:]).max() <= 1e-12 * max(1.0, np.abs(ref[..., 2:]).max())
+    ctx.close()
+
+
+def test_mode_amplitudes_closed_forms_on_device():
+    """x exp(-r^2/2) on a 64^3 grid of [-8, 8]^3: N = pi^(3/2)/2, max e^(-1/2), moments (3/2, 1/2,
+    1/2), parities (-1, +1, +1); a zero field gives zeros; no ground state is needed."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import BdgError, _lib
+    w = W.Workload("3d_64_box", 3, (64, 64, 64), (8.0, 8.0, 8.0), "harmonic3", 10.0, -1.0, 0.0)
+    ctx = make_ctx(w)
+    X, Y, Z = W.coordinates(w)
+    uv = np.zeros((1, 6) + w.shape, dtype=complex)
+    uv[0, 2] = (0.3 - 1j) * X * np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / 2)
+    got = np.array(ctx.mode_amplitudes(torch.from_numpy(uv).to("cuda")))
+    r = got[0, 2]
+    assert np.isclose(r[0], 1.09 * np.pi ** 1.5 / 2, rtol=1e-13)
+    assert np.isclose(r[1], np.sqrt(1.09) * np.exp(-0.5), rtol=1e-13)
+    assert np.allclose(r[2:5], [1.5, 0.5, 0.5], rtol=1e-12)
+    assert np.allclose(r[5:8], [-1.0, 1.0, 1.0], atol=1e-13)
+    assert np.all(got[0, 0] == 0.0)
+    assert ctx.mode_amplitudes(torch.zeros((0, 6) + w.shape, dtype=torch.complex128, device="cuda")) == []
+    import ctypes
+    assert ctx._lib.bdg_mode_amplitudes(ctx._h, -1, None, None) == _lib.BDG_EINVAL
+    ctx.close()
