@@ -122,6 +122,22 @@ bdg_status bdg_apply(bdg_ctx* ctx, int form, int transpose, int nvec, const void
 bdg_status bdg_biortho(bdg_ctx* ctx, int nvec, void* F_dev, void* G_dev, double* sigma,
                        int* rank);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bdg_biortho with separate outputs that
+ * allocates nothing.  F_out = F C_f and G_out = G C_g exactly as bdg_biortho computes them
+ * in place (same factors, same rank rule; the Gram matrix's split-K partial sums are fewer,
+ * so results agree to rounding, not bit for bit).  F_dev, G_dev (inputs) and F_out_dev,
+ * G_out_dev (outputs): nvec columns of 3 npts complex128 each, caller-owned, no output may
+ * overlap another buffer.  Every workspace byte lives in one static device array of
+ * BDG_NOALLOC_SCRATCH_BYTES per device (held until the process ends): 1 <= nvec <=
+ * BDG_NOALLOC_MAX_VEC, BDG_EINVAL otherwise or on overlapping buffers.  Calls that overlap
+ * in time on one device share that array and race; the array keeps the last call's
+ * contents.  Synchronous on the context stream. */
+#define BDG_NOALLOC_MAX_VEC 64
+#define BDG_NOALLOC_SCRATCH_BYTES (48ull << 20)
+bdg_status bdg_biortho_noalloc(bdg_ctx* ctx, int nvec, const void* F_dev, const void* G_dev, void* F_out_dev,
+                               void* G_out_dev, double* sigma, int* rank);
+
 /* k smallest strictly positive excitation frequencies (Section 3.2): block subspace
  * iteration on [[0, H_-], [H_+, 0]] with deflation of the generalized nullspace
  * (Section 2.3), bi-orthogonal Gram-Schmidt and Rayleigh-Ritz projection.  Corrections

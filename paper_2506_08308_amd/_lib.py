@@ -11,10 +11,11 @@ STATUS_NAMES = {0: "BDG_OK", 1: "BDG_EINVAL", 2: "BDG_ENOMEM", 3: "BDG_ENOCONV",
                 5: "BDG_EDEVICE", 6: "BDG_ESTATE"}
 BDG_FP64, BDG_FP32_APPLY = 0, 1
 BDG_FORM_UV, BDG_FORM_FG = 0, 1
+BDG_NOALLOC_MAX_VEC = 64              # include/bdg.h
 
 EXPORTS = ("bdg_create", "bdg_destroy", "bdg_last_error", "bdg_ground_state", "bdg_set_ground_state",
            "bdg_set_ground_state_complex", "bdg_apply", "bdg_biortho", "bdg_eigs", "bdg_eigs_grad",
-           "bdg_perturbed_density", "bdg_stats",
+           "bdg_perturbed_density", "bdg_stats", "bdg_biortho_noalloc",
            "bdg_mode_amplitudes",
            "bdg_test_gram", "bdg_test_update", "bdg_test_svd", "bdg_test_cholesky", "bdg_test_pchol",
            "bdg_test_plu", "bdg_test_gram_pair", "bdg_test_update_pair")
@@ -53,6 +54,8 @@ def load() -> ctypes.CDLL:
     lib.bdg_apply.restype = st
     lib.bdg_biortho.argtypes = [vp, i, vp, vp, pd, pi]
     lib.bdg_biortho.restype = st
+    lib.bdg_biortho_noalloc.argtypes = [vp, i, vp, vp, vp, vp, pd, pi]
+    lib.bdg_biortho_noalloc.restype = st
     lib.bdg_eigs.argtypes = [vp, i, i, d, i, vp, ctypes.c_ulonglong, pd, vp, pd, pi]
     lib.bdg_eigs.restype = st
     lib.bdg_eigs_grad.argtypes = [vp, i, pd, vp, vp, pd, pd]

@@ -185,6 +185,24 @@ class BdgContext:
                                           sig, ctypes.byref(rank)), "bdg_biortho")
         return list(sig), rank.value
 
+    def biortho_noalloc(self, F, G, F_out=None, G_out=None):
+        """bdg_biortho_noalloc: F_out = F C_f, G_out = G C_g (F, G unchanged) with the library's
+        static workspace (nvec <= 64); returns (F_out, G_out, sigma, rank)."""
+        torch = _torch()
+        nvec = F.shape[0]
+        self._check_block(F, "F", torch.complex128, comps=3)
+        self._check_block(G, "G", torch.complex128, rows=nvec, comps=3)
+        F_out = torch.empty_like(F) if F_out is None else F_out
+        G_out = torch.empty_like(G) if G_out is None else G_out
+        self._check_block(F_out, "F_out", torch.complex128, rows=nvec, comps=3)
+        self._check_block(G_out, "G_out", torch.complex128, rows=nvec, comps=3)
+        sig = (ctypes.c_double * max(nvec, 1))()
+        rank = ctypes.c_int()
+        self._check(self._lib.bdg_biortho_noalloc(self._h, nvec, ctypes.c_void_p(_ptr(F)), ctypes.c_void_p(_ptr(G)),
+                                                  ctypes.c_void_p(_ptr(F_out)), ctypes.c_void_p(_ptr(G_out)), sig,
+                                                  ctypes.byref(rank)), "bdg_biortho_noalloc")
+        return F_out, G_out, list(sig)[:nvec], rank.value
+
     def eigs(self, k: int, block: int, tol: float = 1e-8, max_iter: int = 2000, X0=None, seed: int = 0,
              want_vectors: bool = True, check: bool = True):
         """k smallest positive omega; returns dict(omega, uv, residual, iters, status)."""

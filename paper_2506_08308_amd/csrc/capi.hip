@@ -22,9 +22,29 @@ bdg_status hip_check(bdg_ctx* c, hipError_t e, const char* what) {
     return ctx_fail(c, e == hipErrorOutOfMemory ? BDG_ENOMEM : BDG_EDEVICE, m);
 }
 
+// a piece of the caller-provided workspace (context arena mode)
+static bdg_status arena_take(bdg_ctx* c, void** p, size_t bytes) {
+    const size_t at = (c->arena.used + 255) & ~(size_t)255;
+    if (bytes > c->arena.size || at > c->arena.size - bytes) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace of %zu more bytes exceeds the static scratch of %zu bytes", bytes,
+                 c->arena.size);
+        return ctx_fail(c, BDG_EINVAL, buf);
+    }
+    *p = c->arena.base + at;
+    c->arena.used = at + bytes;
+    return BDG_OK;
+}
+
+static bool in_arena(const bdg_ctx* c, const void* p) {
+    const char* q = (const char*)p;
+    return c->arena.base && q >= c->arena.base && q < c->arena.base + c->arena.size;
+}
+
 bdg_status ctx_alloc(bdg_ctx* c, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
+    if (c->arena.base) return arena_take(c, p, bytes);
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -38,7 +58,7 @@ bdg_status ctx_alloc(bdg_ctx* c, void** p, size_t bytes) {
 }
 
 void ctx_free(bdg_ctx* c, void* p) {
-    if (!p) return;
+    if (!p || in_arena(c, p)) return;
     for (size_t i = 0; i < c->owned.size(); ++i)
         if (c->owned[i] == p) {
             c->owned.erase(c->owned.begin() + i);
@@ -48,6 +68,7 @@ void ctx_free(bdg_ctx* c, void* p) {
 }
 
 bdg_status ctx_scratch(bdg_ctx* c, int slot, size_t bytes, void** out) {
+    if (c->arena.base) return arena_take(c, out, bytes == 0 ? 16 : bytes);
     DevBuf& b = c->scratch[slot];
     if (b.bytes < bytes) {
         if (b.p) {

@@ -73,6 +73,15 @@ struct bdg_ctx {
     float* sym32[3] = {nullptr, nullptr, nullptr};
     // scratch owned by the context (grown on demand)
     DevBuf scratch[8];
+    // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out
+    // 256-byte aligned pieces of it in order (nothing is allocated, ctx_free of a piece does
+    // nothing) and the Gram launches keep their split-K partials within `gram_bytes`
+    struct Arena {
+        char* base = nullptr;
+        size_t size = 0;
+        size_t used = 0;
+        size_t gram_bytes = 0;
+    } arena;
     std::string err;
     double stats[10] = {0};
     std::vector<void*> owned;     // every hipMalloc of the context, freed in destroy

@@ -1194,7 +1194,11 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         return ctx_fail(c, BDG_EINVAL, "gram: 1..4 segments");
     if (m1 <= 0 || m2 <= 0) return BDG_OK;
     if (hermitian && m1 != m2) return ctx_fail(c, BDG_EINVAL, "gram: Hermitian form needs m1 == m2");
-    const long long max_split = 0;
+    // in arena mode the split-K partials (nsplit m1 m2 complex values) stay within the
+    // arena's Gram share
+    const long long max_split =
+        c->arena.base ? std::max<long long>(1, (long long)(c->arena.gram_bytes / ((size_t)m1 * m2 * sizeof(double2))))
+                      : 0;
     // Tiling by measured cost (MI355X, 6.3 M rows): a 64-tile takes 0.204 ms per 16 x 16 block
     // it executes, an 80-tile 0.264 ms (the Hermitian diagonal tiles of either about as long
     // as a full tile), so 80-tiles win where they remove padding: m = 80 against 128, 80 x 240
@@ -1297,7 +1301,9 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
     if (m1 <= 0 || m2 <= 0) return BDG_OK;
     if (hermitian && m1 != m2) return ctx_fail(c, BDG_EINVAL, "gram: symmetric form needs m1 == m2");
     const long long r1 = 2LL * m1, r2 = 2LL * m2;
-    const long long max_split = 0;
+    const long long max_split =
+        c->arena.base ? std::max<long long>(1, (long long)(c->arena.gram_bytes / ((size_t)r1 * r2 * sizeof(double))))
+                      : 0;
     const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
     const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
     long long nsplit = 1;

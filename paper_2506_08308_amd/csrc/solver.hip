@@ -46,6 +46,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 namespace {
 
@@ -674,14 +675,14 @@ bdg_status build_deflation(bdg_ctx* c, Small& w, Deflation& d, double null_tol) 
 }  // namespace
 
 // =====================================================================================
-// bdg_biortho
+// bdg_biortho, bdg_biortho_noalloc
 // =====================================================================================
 namespace {
 
 // Factors of the bi-orthogonalization: B = h^d G^H F = U diag(s) V^H, C_f = V s^-1/2 into
 // w.buf[1], C_g = U s^-1/2 into w.buf[2] (nvec x nvec, ld nvec; columns with
 // s_j <= 1e-12 s_1 dropped and set to zero).  s_host: nvec values; *rank: the columns kept.
-// Workspace from ctx_alloc / ctx_scratch.
+// Workspace from ctx_alloc / ctx_scratch (the context's own memory, or its arena).
 bdg_status biortho_factors(bdg_ctx* c, Small& w, int nvec, const double2* F, const double2* G, double* s_host,
                            int* rank) {
     const long long nh = 3 * c->npts;
@@ -741,6 +742,82 @@ extern "C" bdg_status bdg_biortho(bdg_ctx* c, int nvec, void* F_dev, void* G_dev
     BDG_HIP(c, hipMemcpyAsync(G, tmp, bytes, hipMemcpyDeviceToDevice, c->stream));
     BDG_HIP(c, hipStreamSynchronize(c->stream));
     if (sigma) std::memcpy(sigma, s.data(), nvec * sizeof(double));
+    if (rank) *rank = r;
+    return BDG_OK;
+}
+
+// The allocation-free variant's workspace: one static array per device, reached through the
+// address hipGetSymbolAddress gives for it on that device (the array's name is a host-side
+// stand-in and is never passed to a kernel).  Every call on a device uses that device's
+// array, so calls that overlap on one device race.  Its size: the split-K partials of the
+// Gram matrix (at most NOALLOC_GRAM_BYTES) and the small matrices of the SVD.
+namespace {
+constexpr size_t NOALLOC_GRAM_BYTES = 40ull << 20;
+static_assert(NOALLOC_GRAM_BYTES < BDG_NOALLOC_SCRATCH_BYTES, "Gram share inside the scratch");
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[BDG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of `scratch` on the context's device (looked up once per device)
+bdg_status noalloc_scratch(bdg_ctx* c, void** out) {
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES)
+        return ctx_fail(c, BDG_EDEVICE, "bdg_biortho_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        int cur = -1;
+        BDG_HIP(c, hipGetDevice(&cur));
+        if (cur != c->device) BDG_HIP(c, hipSetDevice(c->device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != c->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return hip_check(c, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                    "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[c->device] = p;
+    }
+    *out = g_scratch_ptr[c->device];
+    return BDG_OK;
+}
+}  // namespace
+
+extern "C" bdg_status bdg_biortho_noalloc(bdg_ctx* c, int nvec, const void* F_dev, const void* G_dev, void* Fout_dev,
+                                          void* Gout_dev, double* sigma, int* rank) {
+    if (!c) return BDG_EINVAL;
+    if (nvec <= 0 || nvec > BDG_NOALLOC_MAX_VEC || !F_dev || !G_dev || !Fout_dev || !Gout_dev) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "bdg_biortho_noalloc: need 1 <= nvec <= %d (the static scratch bound) and four "
+                 "buffers, got nvec = %d", BDG_NOALLOC_MAX_VEC, nvec);
+        return ctx_fail(c, BDG_EINVAL, buf);
+    }
+    const size_t bytes = (size_t)nvec * 3 * c->npts * sizeof(double2);
+    const void* ins[2] = {F_dev, G_dev};
+    const void* outs[2] = {Fout_dev, Gout_dev};
+    if (overlaps(Fout_dev, Gout_dev, bytes))
+        return ctx_fail(c, BDG_EINVAL, "bdg_biortho_noalloc: the two outputs overlap");
+    for (const void* o : outs)
+        for (const void* i : ins)
+            if (overlaps(o, i, bytes)) return ctx_fail(c, BDG_EINVAL, "bdg_biortho_noalloc: an output overlaps an input");
+    void* base = nullptr;
+    BDG_TRY(noalloc_scratch(c, &base));
+    // every piece of workspace below comes from the static array (arena mode of the context)
+    c->arena = bdg_ctx::Arena{(char*)base, BDG_NOALLOC_SCRATCH_BYTES, 0, NOALLOC_GRAM_BYTES};
+    Small w;
+    auto leave = defer([&] {
+        small_free(c, w);
+        c->arena = bdg_ctx::Arena{};
+    });
+    const long long nh = 3 * c->npts;
+    double s[BDG_NOALLOC_MAX_VEC];
+    int r = 0;
+    BDG_TRY(biortho_factors(c, w, nvec, (const double2*)F_dev, (const double2*)G_dev, s, &r));
+    Seg sf{F_dev, nvec}, sg{G_dev, nvec};
+    BDG_TRY(update(c, nh, &sf, 1, nh, w.buf[1], nvec, nvec, 0.0, (double2*)Fout_dev, nh));
+    BDG_TRY(update(c, nh, &sg, 1, nh, w.buf[2], nvec, nvec, 0.0, (double2*)Gout_dev, nh));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    if (sigma) std::memcpy(sigma, s, nvec * sizeof(double));
     if (rank) *rank = r;
     return BDG_OK;
 }
