@@ -42,6 +42,9 @@ bdg_status bdg_test_update_pair(bdg_ctx* ctx, long long K, int m, const void* S,
 /* One-sided Jacobi SVD of G (rows x m, ldg), m <= 512: G is replaced by U diag(s) with
  * columns ordered by descending s; V (m x m, ldv) receives V; s (device, m). */
 bdg_status bdg_test_svd(bdg_ctx* ctx, int rows, int m, void* G, int ldg, void* V, int ldv, void* s);
+/* The same for a real G held in complex storage (imaginary parts zero; the projected
+ * matrices of the paired real form): real rotations, V real. */
+bdg_status bdg_test_svd_real(bdg_ctx* ctx, int rows, int m, void* G, int ldg, void* V, int ldv, void* s);
 
 /* In-place lower Cholesky A = L L^H of an m x m Hermitian matrix (upper triangle zeroed);
  * returns BDG_EBREAKDOWN when a pivot is not positive. */

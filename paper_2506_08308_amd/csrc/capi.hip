@@ -257,6 +257,7 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     c->stream = (hipStream_t)hip_stream;
     c->device = dev;
     c->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (const char* e = std::getenv("BDG_APPLY_CHUNK_MB")) c->apply_chunk_bytes = (size_t)std::atoll(e) << 20;
     c->dim = pr->dim;
     c->npts = 1;
     c->hd = 1.0;
@@ -464,6 +465,14 @@ bdg_status bdg_test_svd(bdg_ctx* c, int rows, int m, void* G, int ldg, void* V, 
     if (!c || !G || !V || !s || m < 1 || m > 512 || rows < 1 || ldg < rows || ldv < m)
         return ctx_fail(c, BDG_EINVAL, "bad args");
     BDG_TRY(small_svd(c, rows, m, (double2*)G, ldg, (double2*)V, ldv, (double*)s));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+
+bdg_status bdg_test_svd_real(bdg_ctx* c, int rows, int m, void* G, int ldg, void* V, int ldv, void* s) {
+    if (!c || !G || !V || !s || m < 1 || m > 512 || rows < 1 || ldg < rows || ldv < m)
+        return ctx_fail(c, BDG_EINVAL, "bad args");
+    BDG_TRY(small_svd(c, rows, m, (double2*)G, ldg, (double2*)V, ldv, (double*)s, 1e-13, true));
     BDG_HIP(c, hipStreamSynchronize(c->stream));
     return BDG_OK;
 }

@@ -71,6 +71,10 @@ struct bdg_ctx {
     float2* tw32[3] = {nullptr, nullptr, nullptr};
     double* sym64[3] = {nullptr, nullptr, nullptr};   // mu_m^2 / 2 per axis, FFT order
     float* sym32[3] = {nullptr, nullptr, nullptr};
+    // the operator runs its passes over chunks of vectors whose fields (6 per vector) fit in
+    // this many bytes, so the intermediate passes re-read data still held in the last-level
+    // cache (0: one chunk, all vectors)
+    size_t apply_chunk_bytes = 0;
     // scratch owned by the context (grown on demand)
     DevBuf scratch[8];
     // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out
@@ -208,9 +212,10 @@ bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev)
 bdg_status small_cholesky2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda, int* info0_dev, int* info1_dev);
 // one-sided Jacobi SVD: G (rows x m) -> G V = U diag(s); G overwritten by U diag(s) (columns),
 // V (m x m) receives V, s (m, device) the column norms; columns sorted by descending s.
-// conv: a sweep without rotations of cosine above conv ends the iteration
+// conv: a sweep without rotations of cosine above conv ends the iteration.  real: G has zero
+// imaginary parts (real rotations, V real)
 bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s,
-                     double conv = 1e-13);
+                     double conv = 1e-13, bool real = false);
 
 // pivoted Cholesky of a Gram matrix A (m x m, destroyed; diagonally scaled inside):
 // R (m x m, ld m) gets r columns with R^H A R = I; *rank_dev = r (Schur diagonal cut rtol)

@@ -836,9 +836,25 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double
     double2* A = lg + (size_t)N2 * pg;         // N2 x N2, pitch PA
     double2* J = A + N2 * PA;                  // N2 x N2, pitch PA
     if (t == 0) rot_any = 0;
-    for (int e = t; e < N2 * rows; e += nt) {
-        const int k = e / rows, i = e % rows;
-        lg[k * pg + i] = valid(k) ? G[(long long)colidx(k) * ldg + i] : mkc(0.0, 0.0);
+    {
+        // 256 / N2 threads per column, 8 loads in flight per thread (the round is latency-bound)
+        constexpr int TPC = 256 / N2, U = 8;
+        const int kc = t / TPC, lane = t % TPC;
+        const bool vk = valid(kc);
+        const double2* src = G + (long long)(vk ? colidx(kc) : 0) * ldg;
+        for (int i0 = lane; i0 < rows; i0 += U * TPC) {
+            double2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * TPC;
+                v[u] = (vk && i < rows) ? src[i] : mkc(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * TPC;
+                if (i < rows) lg[kc * pg + i] = v[u];
+            }
+        }
     }
     __syncthreads();
     for (int e = t; e < N2 * N2; e += nt) {
@@ -935,6 +951,153 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double
             }
             if (isg) G[(long long)colidx(c) * ldg + ii] = mkc(sx, sy);
             else V[(long long)colidx(c) * ldv + ii] = mkc(sx, sy);
+        }
+    }
+    if (t == 0 && rot_any) atomicAdd(rotations, 1);
+}
+
+// The same round for real matrices held in complex storage (imaginary parts zero, as in the
+// paired real form): real rotations (the phase e reduces to the sign of the off-diagonal
+// entry), staging of the real parts only (half the LDS), a quarter of the flops.  Staging
+// and the V rows keep several loads in flight per thread: the round is latency-bound.
+template <int W>
+__global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double2* G, int ldg, double2* V, int ldv,
+                                                         int nblk, int rnd, const double* __restrict__ frob2,
+                                                         int* rotations, double conv) {
+    constexpr int N2 = 2 * W, PA = N2 + 1, TPC = 256 / N2, U = 8;
+    static_assert(256 % N2 == 0, "columns divide the workgroup");
+    extern __shared__ double smr[];
+    __shared__ double prm[W][3];
+    __shared__ int pact[W];
+    __shared__ int rot_any;
+    const int t = threadIdx.x;
+    auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (nblk - 1)) + 1; };
+    const int P = player(blockIdx.x), Q = player(nblk - 1 - blockIdx.x);
+    const int c0[2] = {P * W, Q * W};
+    int nc[2];
+    for (int h = 0; h < 2; ++h) {
+        const int lim = m - c0[h];
+        nc[h] = lim <= 0 ? 0 : (lim < W ? lim : W);
+    }
+    auto valid = [&](int k) { return (k % W) < nc[k / W]; };
+    auto colidx = [&](int k) { return c0[k / W] + (k % W); };
+    const int pg = rows | 1;
+    double* lg = smr;                          // N2 columns of G, pitch pg
+    double* A = lg + (size_t)N2 * pg;          // N2 x N2, pitch PA
+    double* J = A + N2 * PA;                   // N2 x N2, pitch PA
+    if (t == 0) rot_any = 0;
+    {
+        // TPC threads per column, U loads in flight per thread
+        const int kc = t / TPC, lane = t % TPC;
+        const bool vk = valid(kc);
+        const double2* src = G + (long long)(vk ? colidx(kc) : 0) * ldg;
+        for (int i0 = lane; i0 < rows; i0 += U * TPC) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * TPC;
+                v[u] = (vk && i < rows) ? src[i].x : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * TPC;
+                if (i < rows) lg[kc * pg + i] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < N2 * N2; e += 256) {
+        const int r = e % N2, c = e / N2;
+        if (r <= c) {
+            const double* a = lg + r * pg;
+            const double* b = lg + c * pg;
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            int i = 0;
+            for (; i + 4 <= rows; i += 4) {
+                s0 += a[i] * b[i];
+                s1 += a[i + 1] * b[i + 1];
+                s2 += a[i + 2] * b[i + 2];
+                s3 += a[i + 3] * b[i + 3];
+            }
+            for (; i < rows; ++i) s0 += a[i] * b[i];
+            const double sx = (s0 + s1) + (s2 + s3);
+            A[c * PA + r] = sx;
+            A[r * PA + c] = sx;
+        }
+        J[c * PA + r] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double negl = 1e-30 * (*frob2);
+    const double tol = 1e-15;
+    constexpr int tpp = 256 / W;
+    const int pair = t / tpp, sub = t % tpp;
+    for (int r2 = 0; r2 < N2 - 1; ++r2) {
+        auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (N2 - 1)) + 1; };
+        int p = pl(pair), q = pl(N2 - 1 - pair);
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        if (sub == 0) {
+            int act = 0;
+            if (valid(p) && valid(q)) {
+                const double al = A[p * PA + p], be = A[q * PA + q];
+                const double gm = A[q * PA + p];
+                const double g = fabs(gm);
+                if (g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
+                    if (g > conv * sqrt(al * be)) rot_any = 1;
+                    const double zeta = (be - al) / (2.0 * g);
+                    const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
+                                                         : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                    prm[pair][0] = cs;
+                    prm[pair][1] = cs * tt;
+                    prm[pair][2] = gm >= 0.0 ? 1.0 : -1.0;    // e = sign(gamma)
+                    act = 1;
+                }
+            }
+            pact[pair] = act;
+        }
+        __syncthreads();
+        const bool act = pact[pair];
+        double cs = 0, sn = 0, ex = 0;
+        if (act) { cs = prm[pair][0]; sn = prm[pair][1]; ex = prm[pair][2]; }
+        if (act) {
+            // columns p, q of A and J: [a, b] <- [cs a - sn e b, sn a + cs e b]
+            for (int i = sub; i < N2; i += tpp) {
+                double a = A[p * PA + i], b = ex * A[q * PA + i];
+                A[p * PA + i] = cs * a - sn * b;
+                A[q * PA + i] = sn * a + cs * b;
+                a = J[p * PA + i];
+                b = ex * J[q * PA + i];
+                J[p * PA + i] = cs * a - sn * b;
+                J[q * PA + i] = sn * a + cs * b;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // rows p, q of A
+            for (int j = sub; j < N2; j += tpp) {
+                const double a = A[j * PA + p], b = ex * A[j * PA + q];
+                A[j * PA + p] = cs * a - sn * b;
+                A[j * PA + q] = sn * a + cs * b;
+            }
+        }
+        __syncthreads();
+    }
+    // [G; V] columns <- [G; V] columns J (each thread owns whole rows)
+    for (int i = t; i < rows + m; i += 256) {
+        const bool isg = i < rows;
+        const int ii = isg ? i : i - rows;
+        double x[N2];
+#pragma unroll
+        for (int k = 0; k < N2; ++k)
+            x[k] = isg ? lg[k * pg + ii] : (valid(k) ? V[(long long)colidx(k) * ldv + ii].x : 0.0);
+#pragma unroll
+        for (int c = 0; c < N2; ++c) {
+            if (!valid(c)) continue;
+            double sx = 0;
+#pragma unroll
+            for (int k = 0; k < N2; ++k) sx += x[k] * J[c * PA + k];
+            if (isg) G[(long long)colidx(c) * ldg + ii] = mkc(sx, 0.0);
+            else V[(long long)colidx(c) * ldv + ii] = mkc(sx, 0.0);
         }
     }
     if (t == 0 && rot_any) atomicAdd(rotations, 1);
@@ -1424,10 +1587,10 @@ bdg_status small_cholesky2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda,
     return hip_check(c, hipGetLastError(), "k_small_cholesky");
 }
 
-bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s, double conv) {
+bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s, double conv,
+                     bool real) {
     if (m <= 0) return BDG_OK;
     if (m > 512 || rows > 512) return ctx_fail(c, BDG_EINVAL, "small_svd: size out of range");
-    // block width: both blocks of G (rows) and V (m) must fit in the workgroup's LDS
     static int lds_limit = 0;
     if (lds_limit == 0) {
         int v = 0;
@@ -1437,11 +1600,13 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
     }
     // block width W: the 2W staged columns of G and the two 2W x 2W matrices (Gram and the
     // accumulated rotation) must fit in the workgroup's LDS
+    const size_t esz = real ? sizeof(double) : sizeof(double2);
     auto lds_need = [&](int w) {
-        return ((size_t)2 * w * (size_t)(rows | 1) + (size_t)2 * (2 * w) * (2 * w + 1)) * sizeof(double2) + 1024;
+        return ((size_t)2 * w * (size_t)(rows | 1) + (size_t)2 * (2 * w) * (2 * w + 1)) * esz + 1024;
     };
-    // W = 8 measured fastest on the 2-D and 3-D solves (more workgroups per round, shorter
-    // inner sweeps); 16 and 4 are kept for the LDS fallback
+    // W = 8 measured fastest on the 2-D and 3-D solves and on 80..240-column real matrices
+    // (a round's time grows with W^2, the number of rounds falls with W); 16 and 4 are kept
+    // for the LDS fallback
     int w = 8;
     while (w > 4 && lds_need(w) > (size_t)lds_limit) w >>= 1;
     if (lds_need(w) > (size_t)lds_limit)
@@ -1457,21 +1622,26 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
                        frob2, counter);
     BDG_HIP(c, hipGetLastError());
     const size_t lds = lds_need(w) - 1024;
-    const void* kern = w == 16 ? (const void*)k_bjacobi_round_g<16>
-                     : w == 8 ? (const void*)k_bjacobi_round_g<8> : (const void*)k_bjacobi_round_g<4>;
+    const void* kern = real ? (w == 16 ? (const void*)k_bjacobi_round_r<16>
+                               : w == 8 ? (const void*)k_bjacobi_round_r<8> : (const void*)k_bjacobi_round_r<4>)
+                            : (w == 16 ? (const void*)k_bjacobi_round_g<16>
+                               : w == 8 ? (const void*)k_bjacobi_round_g<8> : (const void*)k_bjacobi_round_g<4>);
     BDG_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+#define BDG_ROUND(KN, WV)                                                                                         \
+    hipLaunchKernelGGL(KN<WV>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V, ldv, nblk, rnd,   \
+                       (const double*)frob2, counter, conv)
     for (int sweep = 0; sweep < 40; ++sweep) {
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, counter);
         for (int rnd = 0; rnd < nblk - 1; ++rnd) {
-            if (w == 16)
-                hipLaunchKernelGGL(k_bjacobi_round_g<16>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
-                                   ldv, nblk, rnd, (const double*)frob2, counter, conv);
-            else if (w == 8)
-                hipLaunchKernelGGL(k_bjacobi_round_g<8>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
-                                   ldv, nblk, rnd, (const double*)frob2, counter, conv);
-            else
-                hipLaunchKernelGGL(k_bjacobi_round_g<4>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V,
-                                   ldv, nblk, rnd, (const double*)frob2, counter, conv);
+            if (real) {
+                if (w == 16) BDG_ROUND(k_bjacobi_round_r, 16);
+                else if (w == 8) BDG_ROUND(k_bjacobi_round_r, 8);
+                else BDG_ROUND(k_bjacobi_round_r, 4);
+            } else {
+                if (w == 16) BDG_ROUND(k_bjacobi_round_g, 16);
+                else if (w == 8) BDG_ROUND(k_bjacobi_round_g, 8);
+                else BDG_ROUND(k_bjacobi_round_g, 4);
+            }
         }
         BDG_HIP(c, hipGetLastError());
         int h = 0;
@@ -1479,6 +1649,7 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
         BDG_HIP(c, hipStreamSynchronize(c->stream));
         if (h == 0) break;
     }
+#undef BDG_ROUND
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 1, ((size_t)rows * m + (size_t)m * m) * sizeof(double2), &ws));
     hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, c->stream, rows, m, G, ldg, V, ldv, s, (double2*)ws,

@@ -165,6 +165,7 @@ __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<
 // Strided pass along axis y (axis=1) or z (axis=2), tiles of TX adjacent x columns.
 // MODE 0: plain FFT; MODE 1: fused forward * multiplier * inverse (last axis).
 // ----------------------------------------------------------------------------------------
+// TX adjacent x columns per tile (16: 32 complex64 columns measured slower on the fused z pass)
 template <typename V, int N> struct StridedCfg {
     static constexpr int TXA = 2048 / N;
     static constexpr int TX = TXA < 16 ? (TXA < 1 ? 1 : TXA) : 16;
@@ -229,156 +230,173 @@ template <int N> struct CoupleCfg {
     static constexpr int THREADS = 6 * QL * (N / 4) / FH;
 };
 
-template <typename V, int N, int FORM, int TRANS, bool FULL>
+// NVB vectors per workgroup, one after the other through the same LDS: the coefficient
+// fields of the workgroup's points are read once for all of them.
+template <typename V, int N, int FORM, int TRANS, bool FULL, int NVB>
 __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAddr<V> yout,
-                                                 long long lines_per_field, long long nlinegroups,
+                                                 long long lines_per_field, long long nlinegroups, long long nvec,
                                                  const V* __restrict__ tw, MultSpec ms, int ny,
                                                  const decltype(V::x)* __restrict__ coef) {
     using R = decltype(V::x);
     constexpr int Q = N / 4;
     constexpr int QL = CoupleCfg<N>::QL;
     constexpr int FH = CoupleCfg<N>::FH;
+    constexpr int NT = CoupleCfg<N>::THREADS;
+    constexpr int PPT = (QL * N + NT - 1) / NT;       // grid points per thread
+    constexpr int NC = FORM >= 2 ? 21 : 12;          // coefficient fields
     __shared__ V lds[6 * QL * N];
     const int t = threadIdx.x;
     const int fld0 = t / (QL * Q);            // fields fld0 + h * (6 / FH), h < FH
     const int q = (t / Q) % QL;
     const int i = t % Q;
     const long long b = blockIdx.x;
-    const long long vec = b / nlinegroups;
+    const long long vg = b / nlinegroups;
     const long long l0 = (b % nlinegroups) * QL;
     const long long l = l0 + q;
     const bool valid = l < lines_per_field;
     const long long npts = xin.npts;
-    V v[FH][4];
+    // coefficients of this thread's grid points
+    R cf[PPT][NC];
 #pragma unroll
-    for (int h = 0; h < FH; ++h) {
-        const int fld = fld0 + h * (6 / FH);
-        if (FULL) {
-            const V* src = xin.field(vec * 6 + fld) + l * N;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
-            line_fft<V, N, false>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
-            const int my = (int)(l % ny), mz = (int)(l / ny);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[h][r] = cscale(v[h][r], multiplier<R>(ms, i + r * Q, my, mz));
-        } else {
-            const V* src = yout.field(vec * 6 + fld) + l * N;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
-        }
-        line_fft<V, N, true>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < FH; ++h) {
-        const int fld = fld0 + h * (6 / FH);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) lds[(fld * QL + q) * N + i + r * Q] = v[h][r];
-    }
-    __syncthreads();
-    // coupling: one grid point per thread iteration
-    const V* x0 = xin.field(vec * 6 + 0);
-    const V* x3 = xin.field(vec * 6 + 3);
-    V* y0 = yout.field(vec * 6 + 0);
-    V* y3 = yout.field(vec * 6 + 3);
-    for (int pt = t; pt < QL * N; pt += blockDim.x) {
+    for (int k = 0; k < PPT; ++k) {
+        const int pt = t + k * NT;
         const int qq = pt / N, e = pt % N;
-        const long long ll = l0 + qq;
-        if (ll >= lines_per_field) continue;
-        const long long p = ll * N + e;
-        V xa[3], xb[3], ta[3], tb[3];
+        const bool ok = pt < QL * N && l0 + qq < lines_per_field;
+        const long long p = (l0 + qq) * N + e;
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            xa[cc] = x0[cc * npts + p];
-            xb[cc] = x3[cc * npts + p];
-            ta[cc] = lds[(cc * QL + qq) * N + e];
-            tb[cc] = lds[((cc + 3) * QL + qq) * N + e];
-        }
-        V ya[3], yb[3];
-        if constexpr (FORM >= 2) {
-            // complex ground state: A Hermitian (real diagonal, upper 01, 02, 12), B symmetric
-            R ad[3], ao[6], bb[12];
+        for (int s2 = 0; s2 < NC; ++s2) cf[k][s2] = ok ? coef[s2 * npts + p] : (R)0;
+    }
+    for (int vi = 0; vi < NVB; ++vi) {
+        const long long vec = vg * NVB + vi;
+        if (vec >= nvec) break;                      // uniform over the workgroup
+        if (vi > 0) __syncthreads();                 // the previous vector's LDS reads are done
+        V v[FH][4];
 #pragma unroll
-            for (int s = 0; s < 3; ++s) ad[s] = coef[s * npts + p];
+        for (int h = 0; h < FH; ++h) {
+            const int fld = fld0 + h * (6 / FH);
+            if (FULL) {
+                const V* src = xin.field(vec * 6 + fld) + l * N;
 #pragma unroll
-            for (int s = 0; s < 6; ++s) ao[s] = coef[(3 + s) * npts + p];
+                for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
+                line_fft<V, N, false>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
+                const int my = (int)(l % ny), mz = (int)(l / ny);
 #pragma unroll
-            for (int s = 0; s < 12; ++s) bb[s] = coef[(9 + s) * npts + p];
-            auto aent = [&](int a, int c2) -> V {
-                if (a == c2) return cmk<V>(ad[a], 0);
-                const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
-                const int e = lo == 0 ? hi - 1 : 2;                 // 01 -> 0, 02 -> 1, 12 -> 2
-                const V up = cmk<V>(ao[2 * e], ao[2 * e + 1]);
-                return a < c2 ? up : cmk<V>(up.x, -up.y);
-            };
-            auto bent = [&](int a, int c2) -> V {
-                const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
-                const int e = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-                return cmk<V>(bb[2 * e], bb[2 * e + 1]);
-            };
-            const R sv = FORM == 2 ? (R)-1 : (R)1;
+                for (int r = 0; r < 4; ++r) v[h][r] = cscale(v[h][r], multiplier<R>(ms, i + r * Q, my, mz));
+            } else {
+                const V* src = yout.field(vec * 6 + fld) + l * N;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                V su = ta[a], sw = tb[a];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    const V A_ = aent(a, cc), B_ = bent(a, cc);
-                    // u row: A u + B v;  v row: conj(B) u + conj(A) v
-                    su = cadd(su, cadd(cmul(A_, xa[cc]), cmul(B_, xb[cc])));
-                    sw = cadd(sw, cadd(cmul(cmk<V>(B_.x, -B_.y), xa[cc]), cmul(cmk<V>(A_.x, -A_.y), xb[cc])));
-                }
-                ya[a] = su;
-                yb[a] = cmk<V>(sv * sw.x, sv * sw.y);
+                for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
             }
-        } else {
-        R P[6], M[6];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            P[s] = coef[s * npts + p];
-            M[s] = coef[(6 + s) * npts + p];
+            line_fft<V, N, true>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
         }
-        // symmetric 3x3 from 6 entries (00, 01, 02, 11, 12, 22)
-        auto sym = [](const R* S, int a, int c2) -> R {
-            const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
-            const int idx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-            return S[idx];
-        };
-        if (FORM == 1) {
-            const R* Pa = TRANS ? M : P;   // operator acting on f (output half 1)
-            const R* Pb = TRANS ? P : M;   // operator acting on g (output half 0)
+        __syncthreads();
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                V s0 = tb[a], s1 = ta[a];
+        for (int h = 0; h < FH; ++h) {
+            const int fld = fld0 + h * (6 / FH);
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    const R mb = sym(Pb, a, cc), ma = sym(Pa, a, cc);
-                    s0 = cmk<V>(s0.x + mb * xb[cc].x, s0.y + mb * xb[cc].y);
-                    s1 = cmk<V>(s1.x + ma * xa[cc].x, s1.y + ma * xa[cc].y);
-                }
-                ya[a] = s0;
-                yb[a] = s1;
+            for (int r = 0; r < 4; ++r) lds[(fld * QL + q) * N + i + r * Q] = v[h][r];
+        }
+        __syncthreads();
+        // coupling: one grid point per thread iteration
+        const V* x0 = xin.field(vec * 6 + 0);
+        const V* x3 = xin.field(vec * 6 + 3);
+        V* y0 = yout.field(vec * 6 + 0);
+        V* y3 = yout.field(vec * 6 + 3);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int pt = t + k * NT;
+            if (pt >= QL * N) continue;
+            const int qq = pt / N, e = pt % N;
+            const long long ll = l0 + qq;
+            if (ll >= lines_per_field) continue;
+            const long long p = ll * N + e;
+            const R* C = cf[k];
+            V xa[3], xb[3], ta[3], tb[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                xa[cc] = x0[cc * npts + p];
+                xb[cc] = x3[cc * npts + p];
+                ta[cc] = lds[(cc * QL + qq) * N + e];
+                tb[cc] = lds[((cc + 3) * QL + qq) * N + e];
             }
-        } else {
-            const R sB = TRANS ? (R)-1 : (R)1;
+            V ya[3], yb[3];
+            if constexpr (FORM >= 2) {
+                // complex ground state: A Hermitian (real diagonal, upper 01, 02, 12), B symmetric
+                const R* ad = C;
+                const R* ao = C + 3;
+                const R* bb = C + 9;
+                auto aent = [&](int a, int c2) -> V {
+                    if (a == c2) return cmk<V>(ad[a], 0);
+                    const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
+                    const int e2 = lo == 0 ? hi - 1 : 2;                 // 01 -> 0, 02 -> 1, 12 -> 2
+                    const V up = cmk<V>(ao[2 * e2], ao[2 * e2 + 1]);
+                    return a < c2 ? up : cmk<V>(up.x, -up.y);
+                };
+                auto bent = [&](int a, int c2) -> V {
+                    const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
+                    const int e2 = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+                    return cmk<V>(bb[2 * e2], bb[2 * e2 + 1]);
+                };
+                const R sv = FORM == 2 ? (R)-1 : (R)1;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                V su = ta[a], sv = tb[a];
+                for (int a = 0; a < 3; ++a) {
+                    V su = ta[a], sw = tb[a];
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    const R pa = sym(P, a, cc), mm = sym(M, a, cc);
-                    const R A_ = (R)0.5 * (pa + mm), B_ = (R)0.5 * (pa - mm) * sB;
-                    su = cmk<V>(su.x + A_ * xa[cc].x + B_ * xb[cc].x, su.y + A_ * xa[cc].y + B_ * xb[cc].y);
-                    sv = cmk<V>(sv.x + B_ * xa[cc].x + A_ * xb[cc].x, sv.y + B_ * xa[cc].y + A_ * xb[cc].y);
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const V A_ = aent(a, cc), B_ = bent(a, cc);
+                        // u row: A u + B v;  v row: conj(B) u + conj(A) v
+                        su = cadd(su, cadd(cmul(A_, xa[cc]), cmul(B_, xb[cc])));
+                        sw = cadd(sw, cadd(cmul(cmk<V>(B_.x, -B_.y), xa[cc]), cmul(cmk<V>(A_.x, -A_.y), xb[cc])));
+                    }
+                    ya[a] = su;
+                    yb[a] = cmk<V>(sv * sw.x, sv * sw.y);
                 }
-                ya[a] = su;
-                yb[a] = cmk<V>(-sv.x, -sv.y);
-            }
-        }
-        }
+            } else {
+                const R* P = C;
+                const R* M = C + 6;
+                // symmetric 3x3 from 6 entries (00, 01, 02, 11, 12, 22)
+                auto sym = [](const R* S, int a, int c2) -> R {
+                    const int lo = a < c2 ? a : c2, hi = a < c2 ? c2 : a;
+                    const int idx = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+                    return S[idx];
+                };
+                if (FORM == 1) {
+                    const R* Pa = TRANS ? M : P;   // operator acting on f (output half 1)
+                    const R* Pb = TRANS ? P : M;   // operator acting on g (output half 0)
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            y0[cc * npts + p] = ya[cc];
-            y3[cc * npts + p] = yb[cc];
+                    for (int a = 0; a < 3; ++a) {
+                        V s0 = tb[a], s1 = ta[a];
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) {
+                            const R mb = sym(Pb, a, cc), ma = sym(Pa, a, cc);
+                            s0 = cmk<V>(s0.x + mb * xb[cc].x, s0.y + mb * xb[cc].y);
+                            s1 = cmk<V>(s1.x + ma * xa[cc].x, s1.y + ma * xa[cc].y);
+                        }
+                        ya[a] = s0;
+                        yb[a] = s1;
+                    }
+                } else {
+                    const R sB = TRANS ? (R)-1 : (R)1;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        V su = ta[a], sv = tb[a];
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) {
+                            const R pa = sym(P, a, cc), mm = sym(M, a, cc);
+                            const R A_ = (R)0.5 * (pa + mm), B_ = (R)0.5 * (pa - mm) * sB;
+                            su = cmk<V>(su.x + A_ * xa[cc].x + B_ * xb[cc].x, su.y + A_ * xa[cc].y + B_ * xb[cc].y);
+                            sv = cmk<V>(sv.x + B_ * xa[cc].x + A_ * xb[cc].x, sv.y + B_ * xa[cc].y + A_ * xb[cc].y);
+                        }
+                        ya[a] = su;
+                        yb[a] = cmk<V>(-sv.x, -sv.y);
+                    }
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                y0[cc * npts + p] = ya[cc];
+                y3[cc * npts + p] = yb[cc];
+            }
         }
     }
 }
@@ -455,19 +473,52 @@ bdg_status run_couple(bdg_ctx* c, FieldAddr<const V> xin, FieldAddr<V> yout, lon
     using R = decltype(V::x);
     const int N = c->n[0];
     const long long lpf = c->npts / N;
+    // four vectors per workgroup (the coefficients are read once for them) when that still
+    // leaves a few thousand workgroups
+    constexpr int NVB = FULL ? 1 : 4;
     BDG_DISPATCH_N(N, {
         constexpr int QL = CoupleCfg<NN>::QL;
         const long long ngroups = (lpf + QL - 1) / QL;
-        dim3 grid((unsigned)(nvec * ngroups));
-        hipLaunchKernelGGL((k_couple<V, NN, FORM, TRANS, FULL>), grid, dim3(CoupleCfg<NN>::THREADS), 0,
-                           c->stream, xin, yout, lpf, ngroups, (const V*)tw_of<R>(c, 0), ms, c->n[1],
-                           FORM >= 2 ? (const R*)c->ccoef : coef_of<R>(c));
+        const bool wide = ngroups * ((nvec + NVB - 1) / NVB) >= 4096;
+        const int nvb = wide ? NVB : 1;
+        dim3 grid((unsigned)(((nvec + nvb - 1) / nvb) * ngroups));
+        if (wide)
+            hipLaunchKernelGGL((k_couple<V, NN, FORM, TRANS, FULL, NVB>), grid, dim3(CoupleCfg<NN>::THREADS), 0,
+                               c->stream, xin, yout, lpf, ngroups, nvec, (const V*)tw_of<R>(c, 0), ms, c->n[1],
+                               FORM >= 2 ? (const R*)c->ccoef : coef_of<R>(c));
+        else
+            hipLaunchKernelGGL((k_couple<V, NN, FORM, TRANS, FULL, 1>), grid, dim3(CoupleCfg<NN>::THREADS), 0,
+                               c->stream, xin, yout, lpf, ngroups, nvec, (const V*)tw_of<R>(c, 0), ms, c->n[1],
+                               FORM >= 2 ? (const R*)c->ccoef : coef_of<R>(c));
     });
     return hip_check(c, hipGetLastError(), "k_couple");
 }
 
 template <typename V, int FORM, int TRANS>
+bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y);
+
+template <typename V, int FORM, int TRANS>
 bdg_status apply_impl(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y) {
+    int chunk = nvec;
+    if (c->apply_chunk_bytes > 0) {
+        const size_t per_vec = 6 * (size_t)c->npts * sizeof(V);
+        chunk = (int)std::max<size_t>(1, c->apply_chunk_bytes / per_vec);
+    }
+    for (int v0 = 0; v0 < nvec; v0 += chunk) {
+        const int nv = std::min(chunk, nvec - v0);
+        FieldAddr<const V> Xc = X;
+        FieldAddr<V> Yc = Y;
+        Xc.lo += v0 * X.vstride;
+        Xc.hi += v0 * X.vstride;
+        Yc.lo += v0 * Y.vstride;
+        Yc.hi += v0 * Y.vstride;
+        BDG_TRY((apply_chunk<V, FORM, TRANS>(c, nv, Xc, Yc)));
+    }
+    return BDG_OK;
+}
+
+template <typename V, int FORM, int TRANS>
+bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y) {
     MultSpec ms = make_ms(c, 0, 0.0);
     const long long nf = 6LL * nvec;
     if (c->dim == 1) return run_couple<V, FORM, TRANS, true>(c, X, Y, nvec, ms);

@@ -435,7 +435,7 @@ bdg_status rr_once(bdg_ctx* c, Small& w, int m, int nb, const double2* Gf, const
     BDG_TRY(small_cholesky2(c, r, X1, X2, m, w.info, w.info + 1));
     // G = L_K^H L_M -> B ; SVD -> V3, s[3]
     BDG_TRY(small_gemm(c, 1, 0, r, r, r, ONE, X2, m, X1, m, ZERO, B, m));
-    BDG_TRY(small_svd(c, r, r, B, m, V3, m, w.s[3]));
+    BDG_TRY(small_svd(c, r, r, B, m, V3, m, w.s[3], 1e-13, true));
     int info[2];
     std::vector<double> s4(r);
     BDG_TRY(d2h(c, info, w.info, 2 * sizeof(int)));
@@ -1024,14 +1024,45 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
     bool force64 = false;
     std::vector<double> res(nb, 1.0), hn(4 * nb);
     bdg_status final_status = BDG_ENOCONV;
-    double t_apply = 0, t_prec = 0, t_gram = 0, t_small = 0, t_upd = 0;
-    auto now = [] { return std::chrono::steady_clock::now(); };
-    auto ms_since = [&](std::chrono::steady_clock::time_point t0) {
-        return std::chrono::duration<double, std::milli>(now() - t0).count();
+    // phase times from events on the stream (no host synchronization of their own): marks
+    // 0..5 bound correction, apply, Gram, projected problem and update of one iteration; they
+    // are read after the next host synchronization.  BDG_PHASE_SYNC=1 adds a stream
+    // synchronization after every phase (host-side view of the same split).
+    // Two sets alternate, so an iteration records into one while the other waits to be read.
+    double t_phase[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[2][6] = {};
+    for (auto& set : ev)
+        for (auto& e : set) BDG_HIP(c, hipEventCreate(&e));
+    auto ev_free = defer([&] {
+        for (auto& set : ev)
+            for (auto& e : set)
+                if (e) (void)hipEventDestroy(e);
+    });
+    int ev_cur = 0, ev_pending = -1;
+    auto mark = [&](int i) -> bdg_status {
+        BDG_HIP(c, hipEventRecord(ev[ev_cur][i], c->stream));
+        if (i == 5) {
+            ev_pending = ev_cur;
+            ev_cur ^= 1;
+        }
+        return BDG_OK;
     };
-    const bool timing = true;
+    auto collect = [&]() -> bdg_status {
+        if (ev_pending < 0) return BDG_OK;
+        for (int i = 0; i < 5; ++i) {
+            float ms = 0;
+            BDG_HIP(c, hipEventElapsedTime(&ms, ev[ev_pending][i], ev[ev_pending][i + 1]));
+            t_phase[i] += ms;
+        }
+        ev_pending = -1;
+        return BDG_OK;
+    };
+    const bool phase_sync = [] {
+        const char* v = std::getenv("BDG_PHASE_SYNC");
+        return v && v[0] == '1';
+    }();
     auto sync_if = [&]() -> bdg_status {
-        if (timing) BDG_HIP(c, hipStreamSynchronize(c->stream));
+        if (phase_sync) BDG_HIP(c, hipStreamSynchronize(c->stream));
         return BDG_OK;
     };
     std::vector<int> act;
@@ -1042,11 +1073,12 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         double2* HG = S.col(HSG, S.slotF);
         double2* Wf = S.col(SF, S.slotW);
         double2* Wg = S.col(SG, S.slotW);
-        auto t0 = now();
         // residual norms of every column in one pass over F, G and their images
+        BDG_TRY(mark(0));
         BDG_TRY(h2d(c, d_om, om.data(), nb * sizeof(double)));
         BDG_TRY(resnorm2_pair(c, nh, nbc, HF, G, HG, F, nh, d_om, d_n));
         BDG_TRY(d2h(c, hn.data(), d_n, 4 * nb * sizeof(double)));
+        BDG_TRY(collect());
         double rmax = 0;
         bool all_k = true;
         act.clear();
@@ -1187,8 +1219,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         }
         BDG_HIP(c, hipGetLastError());
         BDG_TRY(sync_if());
-        t_prec += ms_since(t0);
-        auto t1 = now();
+        BDG_TRY(mark(1));
         double2* HWf = S.col(HSF, S.slotW);
         double2* HWg = S.col(HSG, S.slotW);
         const bool w32img = mixed && !force64;
@@ -1235,8 +1266,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
             napply64 += nact;
         }
         BDG_TRY(sync_if());
-        t_apply += ms_since(t1);
-        auto t2 = now();
+        BDG_TRY(mark(2));
         // Gram matrices of [F, W, P] (W and P: active columns)
         const int ns = np > 0 ? 3 : 2;
         const int mc = nb + nact + np;
@@ -1247,8 +1277,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         Seg hg[3] = {{HG, nbc}, {HWg, nactc}, {npc ? S.col(HSG, S.slotP) : nullptr, npc}};
         BDG_TRY(grams(sf, sg, hf, hg, ns, mc, w32img));
         BDG_TRY(sync_if());
-        t_gram += ms_since(t2);
-        auto t3 = now();
+        BDG_TRY(mark(3));
         const bool f32img = mixed && !refreshed && !force64;
         std::vector<double> om_prev = om;
         bdg_status rst = rayleigh_ritz(c, w, mc, nb, Gf, Gg, Br, Mr, Kr, acoef, bcoef, om,
@@ -1265,8 +1294,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
             continue;
         }
         if (rst != BDG_OK) { final_status = rst; break; }
-        t_small += ms_since(t3);
-        auto t4 = now();
+        BDG_TRY(mark(4));
         // updates: P_new = [W, P] a[nb:] into the free slot, then F_new = F a[:nb] + P_new
         // into W's slot (W is no longer read), so no output overlaps an input
         const int dst_P = S.slotFree, dst_F = S.slotW;
@@ -1289,7 +1317,7 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         S.slotFree = (oldP >= 0) ? oldP : S.slotFree2;
         S.slotFree2 = -1;
         BDG_TRY(sync_if());
-        t_upd += ms_since(t4);
+        BDG_TRY(mark(5));
     }
     if (converged) final_status = BDG_OK;
     F = S.col(SF, S.slotF);
@@ -1316,12 +1344,13 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         BDG_HIP(c, hipGetLastError());
     }
     BDG_HIP(c, hipStreamSynchronize(c->stream));
-    c->stats[0] = ms_since(t_start);
-    c->stats[1] = t_apply;
-    c->stats[2] = t_prec;
-    c->stats[3] = t_gram;
-    c->stats[4] = t_small;
-    c->stats[5] = t_upd;
+    BDG_TRY(collect());
+    c->stats[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    c->stats[1] = t_phase[1];
+    c->stats[2] = t_phase[0];
+    c->stats[3] = t_phase[2];
+    c->stats[4] = t_phase[3];
+    c->stats[5] = t_phase[4];
     c->stats[7] = std::min(it, max_iter);
     c->stats[8] = napply64;
     c->stats[9] = napply32;

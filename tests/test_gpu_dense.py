@@ -103,6 +103,37 @@ def test_jacobi_svd_matches_numpy(rows, m):
     ctx.close()
 
 
+@pytest.mark.parametrize("rows,m,spread", [(6, 6, 1.0), (40, 40, 3.0), (37, 24, 2.0), (240, 240, 3.6),
+                                           (17, 33, 1.0), (161, 161, 3.6)])
+def test_jacobi_svd_real_matches_numpy(rows, m, spread):
+    """Real variant (paired real form): singular values spread over `spread` decades, as the
+    projected frequencies are; U S = G V, V orthogonal, all parts real."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"svd real {rows}x{m}")
+    ctx = _ctx()
+    rng = np.random.default_rng(11)
+    kk = min(rows, m)
+    Ua, _ = np.linalg.qr(rng.standard_normal((rows, kk)))
+    Va, _ = np.linalg.qr(rng.standard_normal((m, kk)))
+    Gm = (Ua * np.logspace(0.0, -spread, kk)) @ Va.T          # rows x m
+    Gd = torch.from_numpy(Gm.T.astype(np.complex128).copy()).cuda()
+    V = torch.zeros((m, m), dtype=torch.complex128, device="cuda")
+    s = torch.zeros(m, dtype=torch.float64, device="cuda")
+    st = ctx._lib.bdg_test_svd_real(ctx._h, rows, m, _p(Gd), rows, _p(V), m, _p(s))
+    assert st == _lib.BDG_OK
+    s_ref = np.linalg.svd(Gm, compute_uv=False)
+    sh = s.cpu().numpy()
+    assert np.allclose(sh[:kk], s_ref[:kk], rtol=1e-12, atol=1e-14 * s_ref[0])
+    assert np.all(sh[kk:] < 1e-12 * s_ref[0])
+    Vm = V.cpu().numpy().T
+    US = Gd.cpu().numpy().T
+    assert np.abs(Vm.imag).max() == 0 and np.abs(US.imag).max() == 0
+    assert np.abs(Gm @ Vm.real - US.real).max() < 1e-12 * s_ref[0]
+    assert np.abs(Vm.real.T @ Vm.real - np.eye(m)).max() < 1e-12
+    ctx.close()
+
+
 @pytest.mark.parametrize("m", [1, 5, 64, 240])
 def test_cholesky_matches_numpy(m):
     torch = torch_cuda()
