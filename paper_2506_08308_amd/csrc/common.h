@@ -75,6 +75,11 @@ struct bdg_ctx {
     // this many bytes, so the intermediate passes re-read data still held in the last-level
     // cache (0: one chunk, all vectors)
     size_t apply_chunk_bytes = 0;
+    // complex64 (f, g) operator on 128 x 128 x nz grids by xy-plane passes in LDS (three
+    // passes over HBM instead of five)
+    bool apply_planes = true;
+    // symmetric paired Grams of 65..128 complex columns by one workgroup per K-split
+    bool gram_wide = true;
     // scratch owned by the context (grown on demand)
     DevBuf scratch[8];
     // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out

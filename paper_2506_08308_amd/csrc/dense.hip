@@ -296,6 +296,115 @@ __global__ void __launch_bounds__(256) k_gram_pair(long long K, int m1, int m2, 
             }
 }
 
+// Whole-matrix form of the symmetric paired Gram for 64 < m <= 128 complex columns (the
+// Rayleigh-Ritz Grams of a block of 33..64 complex columns): one workgroup of 8 waves holds
+// every upper block pair (bi <= bj, blocks of 16 complex columns) of its K-split, so each
+// input row is staged once per split instead of once per tile row and column, and the
+// arithmetic per staged byte doubles against the 64-column tiles.  Wave w takes a contiguous
+// run of the block pairs (at most WB = 5 of the 36), four accumulators (u, v) per pair.
+constexpr int WGM = 128;        // columns staged per operand
+constexpr int WB = 5;           // block pairs per wave
+__global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m, SegList A, long long lda, SegList B,
+                                                        long long ldb, long long kper, int same,
+                                                        double* __restrict__ part) {
+    __shared__ __align__(16) double la[WGM * GPAD];
+    __shared__ __align__(16) double lb[WGM * GPAD];
+    const long long split = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const long long ldr = 2LL * m;
+    double* out = part + split * ldr * ldr;
+    const double* lbr = same ? la : lb;
+    const long long k0 = split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    // this wave's block pairs: npairs = nb (nb + 1) / 2 in row order, dealt out in runs
+    const int nb = (m + 15) / 16;
+    const int npairs = nb * (nb + 1) / 2;
+    const int base = npairs / 8, extra = npairs % 8;
+    const int first = wave * base + (wave < extra ? wave : extra);
+    const int cnt = base + (wave < extra ? 1 : 0);
+    int bi[WB], bj[WB];
+#pragma unroll
+    for (int j = 0; j < WB; ++j) {
+        int e = first + j, r = 0;
+        while (r < nb && e >= nb - r) {
+            e -= nb - r;
+            ++r;
+        }
+        bi[j] = r;
+        bj[j] = r + e;
+    }
+    d4 acc[WB][4];
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[j][q] = d4{0, 0, 0, 0};
+    // staging: thread t loads complex row lk of columns lc + 32 pass (pass < 4)
+    const int lk = t & 15, lc = t >> 4;
+    const double2* acol[4];
+    const double2* bcol[4];
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int col = lc + 32 * pass;
+        acol[pass] = col < m ? seg_col(A, col, lda) : nullptr;
+        bcol[pass] = (!same && col < m) ? seg_col(B, col, ldb) : nullptr;
+    }
+    double2 ra[4], rb[4];
+    auto gload = [&](long long kc) {
+        const long long kk = kc + lk;
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            ra[pass] = (kk < k1 && acol[pass]) ? acol[pass][kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && bcol[pass]) ? bcol[pass][kk] : double2{0, 0};
+        }
+    };
+    gload(k0);
+    for (long long kc = k0; kc < k1; kc += GKC) {
+        __syncthreads();
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const int col = lc + 32 * pass;
+            *reinterpret_cast<double2*>(&la[col * GPAD + 2 * lk]) = ra[pass];
+            if (!same) *reinterpret_cast<double2*>(&lb[col * GPAD + 2 * lk]) = rb[pass];
+        }
+        __syncthreads();
+        if (kc + GKC < k1) gload(kc + GKC);
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < GKC; ks += 4) {
+            const int kr = 2 * (ks + (lane >> 4));
+            const int ci = lane & 15;
+#pragma unroll
+            for (int j = 0; j < WB; ++j) {
+                if (j >= cnt) break;
+                const double2 av = *reinterpret_cast<const double2*>(&la[(16 * bi[j] + ci) * GPAD + kr]);
+                const double2 bv = *reinterpret_cast<const double2*>(&lbr[(16 * bj[j] + ci) * GPAD + kr]);
+                acc[j][0] = mfma(av.x, bv.x, acc[j][0]);
+                acc[j][1] = mfma(av.x, bv.y, acc[j][1]);
+                acc[j][2] = mfma(av.y, bv.x, acc[j][2]);
+                acc[j][3] = mfma(av.y, bv.y, acc[j][3]);
+            }
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+    // register r of lane l holds D[4 r + l / 16][l % 16]
+#pragma unroll
+    for (int j = 0; j < WB; ++j) {
+        if (j >= cnt) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * bi[j] + 4 * r + (lane >> 4);
+            const int q = 16 * bj[j] + (lane & 15);
+            if (p < m && q < m) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) out[(2LL * q + v) * ldr + 2 * p + u] = acc[j][2 * u + v][r];
+            }
+        }
+    }
+}
+
 // C (m1 x m2 real entries in complex storage, imaginary parts 0) = alpha * sum over the splits
 // of the real partials, in split order; herm mirrors every entry below the diagonal 16 x 16
 // blocks from above (the paired tiles compute those blocks, see k_gram_pair)
@@ -1467,14 +1576,28 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
     const long long max_split =
         c->arena.base ? std::max<long long>(1, (long long)(c->arena.gram_bytes / ((size_t)r1 * r2 * sizeof(double))))
                       : 0;
+    bool same = hermitian && na == nbs && lda == ldb;
+    for (int i = 0; same && i < na; ++i) same = sa[i].p == sb[i].p && sa[i].ncols == sb[i].ncols;
+    if (hermitian && m1 > GT && m1 <= WGM && c->gram_wide) {
+        // one workgroup per split covers the whole matrix: about two workgroups per CU
+        long long nsplit = 1;
+        const long long kper = gram_rows_per_split(K, 1, 2LL * c->ncu, &nsplit, max_split);
+        void* ws = nullptr;
+        BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * r1 * r2 * sizeof(double), &ws));
+        hipLaunchKernelGGL(k_gram_pair_wide, dim3((unsigned)nsplit), dim3(512), 0, c->stream, K, m1, A, lda, B, ldb,
+                           kper, same ? 1 : 0, (double*)ws);
+        BDG_HIP(c, hipGetLastError());
+        const long long tot = r1 * r2;
+        hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, (int)r1,
+                           (int)r2, (int)nsplit, (const double*)ws, alpha, C, ldc, 1);
+        return hip_check(c, hipGetLastError(), "k_gram_pair_wide");
+    }
     const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
     const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
     long long nsplit = 1;
     const long long kper = gram_rows_per_split(K, ntiles, 3LL * c->ncu, &nsplit, max_split);
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * r1 * r2 * sizeof(double), &ws));
-    bool same = hermitian && na == nbs && lda == ldb;
-    for (int i = 0; same && i < na; ++i) same = sa[i].p == sb[i].p && sa[i].ncols == sb[i].ncols;
     const long long total = nsplit * ntiles;
     const long long per_xcd = (total + 7) / 8;
     const int h = hermitian ? 1 : 0, sm = same ? 1 : 0;

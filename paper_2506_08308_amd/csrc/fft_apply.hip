@@ -16,6 +16,8 @@
 // extra exchange.  Twiddles exp(-2 pi i m/N) come from host-built float64 tables.
 #include "common.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
@@ -49,10 +51,38 @@ template <typename V, bool INV> __device__ __forceinline__ void dft4(V v[4]) {
     v[3] = csub(t1, t3);
 }
 
+// Workgroup barrier that orders LDS accesses only: the wave waits for its own LDS operations
+// (lgkmcnt 0) and meets the others; global loads still in flight stay in flight (a full
+// __syncthreads waits for them too), which lets a workgroup prefetch its next input while it
+// transforms the current one in LDS.
+__device__ __forceinline__ void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);      // vmcnt, expcnt at their maxima, lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Ordering of the LDS exchanges of line_fft.  SYNC_BLOCK: __syncthreads.  SYNC_WAVE: every
+// line lies within one wave (its N/4 threads are consecutive and N/4 <= 64); a wave's LDS
+// operations are executed in issue order, so waiting for its own (lgkmcnt 0) suffices and
+// no workgroup barrier is taken.
+enum { SYNC_BLOCK = 0, SYNC_WAVE = 2 };
+template <int SYNC> __device__ __forceinline__ void fft_sync() {
+    if constexpr (SYNC == SYNC_BLOCK) {
+        __syncthreads();
+    } else {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+}
+// wave-local exchanges for contiguous lines of up to 256 points
+template <int N> constexpr int contiguous_sync() { return N / 4 <= 64 ? SYNC_WAVE : SYNC_BLOCK; }
+
 // In-line FFT of length N.  On entry v[r] = x[i + r N/4]; on exit v[r] = X[i + r N/4].
-// lds(e) = lds[lb + e * ls] is this line's exchange buffer.  Every thread of the block
-// must call it (barriers), including threads whose line is out of range.
-template <typename V, int N, bool INV>
+// lds(e) = lds[lb + e * ls] is this line's exchange buffer.  With SYNC_BLOCK every thread of
+// the block must call it (barriers), including threads whose line is out of range.
+template <typename V, int N, bool INV, int SYNC = SYNC_BLOCK>
 __device__ __forceinline__ void line_fft(V v[4], int i, V* __restrict__ lds, int lb, int ls,
                                          const V* __restrict__ tw) {
     constexpr int Q = N / 4;
@@ -72,10 +102,10 @@ __device__ __forceinline__ void line_fft(V v[4], int i, V* __restrict__ lds, int
         const bool last = (s == NP4 - 1) && !R2;
         if (!last) {
             const int j = ((i - k) << 2) + k;
-            __syncthreads();
+            fft_sync<SYNC>();
 #pragma unroll
             for (int r = 0; r < 4; ++r) lds[lb + (j + r * p) * ls] = v[r];
-            __syncthreads();
+            fft_sync<SYNC>();
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = lds[lb + (i + r * Q) * ls];
         }
@@ -142,14 +172,15 @@ __global__ void __launch_bounds__(256) k_xpass(FieldAddr<const V> in, FieldAddr<
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], wv[r]);
     }
+    constexpr int SY = contiguous_sync<N>();
     if (MODE == 0) {
-        line_fft<V, N, INV>(v, i, lds, ln * N, 1, tw);
+        line_fft<V, N, INV, SY>(v, i, lds, ln * N, 1, tw);
     } else {
-        line_fft<V, N, false>(v, i, lds, ln * N, 1, tw);
+        line_fft<V, N, false, SY>(v, i, lds, ln * N, 1, tw);
         const int my = (int)(l % ny), mz = (int)(l / ny);
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = cscale(v[r], multiplier<R>(ms, i + r * Q, my, mz));
-        line_fft<V, N, true>(v, i, lds, ln * N, 1, tw);
+        line_fft<V, N, true, SY>(v, i, lds, ln * N, 1, tw);
     }
     if (winv) {
 #pragma unroll
@@ -244,6 +275,8 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
     constexpr int NT = CoupleCfg<N>::THREADS;
     constexpr int PPT = (QL * N + NT - 1) / NT;       // grid points per thread
     constexpr int NC = FORM >= 2 ? 21 : 12;          // coefficient fields
+    // one line per thread group (FH = 1): contiguous lines, wave-local exchanges up to N = 256
+    constexpr int SYC = FH == 1 ? contiguous_sync<N>() : SYNC_BLOCK;
     __shared__ V lds[6 * QL * N];
     const int t = threadIdx.x;
     const int fld0 = t / (QL * Q);            // fields fld0 + h * (6 / FH), h < FH
@@ -278,7 +311,7 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
                 const V* src = xin.field(vec * 6 + fld) + l * N;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
-                line_fft<V, N, false>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
+                line_fft<V, N, false, SYC>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
                 const int my = (int)(l % ny), mz = (int)(l / ny);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[h][r] = cscale(v[h][r], multiplier<R>(ms, i + r * Q, my, mz));
@@ -287,7 +320,7 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[h][r] = valid ? src[i + r * Q] : cmk<V>(0, 0);
             }
-            line_fft<V, N, true>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
+            line_fft<V, N, true, SYC>(v[h], i, lds, (fld * QL + q) * N, 1, tw);
         }
         __syncthreads();
 #pragma unroll
@@ -398,6 +431,175 @@ __global__ void __launch_bounds__(1024) k_couple(FieldAddr<const V> xin, FieldAd
                 y3[cc * npts + p] = yb[cc];
             }
         }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// xy-plane passes (complex64, nx = ny = 128, 3-D): one workgroup holds a whole 128 x 128
+// plane in LDS (row pitch 129 keeps the column accesses of the y transform free of bank
+// conflicts), so the x and y transforms share one pass over HBM.  With the z pass between
+// them the (f, g) operator takes three passes instead of five:
+//   plane-fwd:  Y[sigma(s)] = F_xy X[s]  (sigma swaps the f and g halves, see below)
+//   z pass:     Y <- F_z^-1 k2 F_z Y     (k_strided, MODE 1)
+//   plane-inv:  Y[o] = F_xy^-1 Y[o] + sum_c C_o(a, c) X[h(o), c]
+// Output field o (half 0: y_f = T g + H_- g, half 1: y_g = T f + H_+ f) needs the kinetic
+// image of the field of the other half with the same component, so the forward pass stores
+// it at o's position and the inverse pass reads and writes one position only.
+// The kernels are persistent (one workgroup per CU: the plane takes 129 KiB of LDS) and keep
+// the next plane's 16 loads per thread in flight while the current plane is transformed
+// (LDS-only barriers in between).
+// ----------------------------------------------------------------------------------------
+constexpr int PLN = 128, PLP = 129;
+constexpr size_t PLANE_LDS = (size_t)PLN * PLP * sizeof(float2);
+
+// rows (MODE 0: x transform) or columns (MODE 1: y transform) of the LDS plane, 32 lines per
+// round (a line on 32 consecutive lanes of one wave: wave-local exchanges), four rounds, one
+// workgroup barrier at the end
+template <bool INV, int MODE>
+__device__ __forceinline__ void plane_lines(float2* pl, const float2* __restrict__ tw) {
+    constexpr int Q = PLN / 4;
+    const int t = threadIdx.x;
+    const int ln = t / Q, i = t % Q;
+#pragma unroll 1
+    for (int rnd = 0; rnd < 4; ++rnd) {
+        const int line = rnd * 32 + ln;
+        const int lb = MODE == 0 ? line * PLP : line;
+        const int ls = MODE == 0 ? 1 : PLP;
+        float2 v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = pl[lb + (i + r * Q) * ls];
+        line_fft<float2, PLN, INV, SYNC_WAVE>(v, i, pl, lb, ls, tw);
+        fft_sync<SYNC_WAVE>();   // the exchange buffer of the line is the line itself
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pl[lb + (i + r * Q) * ls] = v[r];
+    }
+    lds_barrier();
+}
+
+__device__ __forceinline__ void plane_load(float2 (&v)[16], const float2* __restrict__ src) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = src[t + 1024 * j];
+}
+
+__device__ __forceinline__ void plane_to_lds(float2* pl, const float2 (&v)[16]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = t + 1024 * j;
+        pl[(e >> 7) * PLP + (e & 127)] = v[j];
+    }
+}
+
+// forward: task w = (field f, plane z), f-major; Y[sigma(f)] plane z = F_xy X[f] plane z
+__global__ void __launch_bounds__(1024) k_plane_fwd(FieldAddr<const float2> in, FieldAddr<float2> out,
+                                                   long long nfields, int nz, const float2* __restrict__ twx,
+                                                   const float2* __restrict__ twy) {
+    extern __shared__ float2 pl[];
+    const long long ntask = nfields * nz;
+    long long w = blockIdx.x;
+    if (w >= ntask) return;
+    const int t = threadIdx.x;
+    float2 v[16];
+    plane_load(v, in.field(w / nz) + (w % nz) * (long long)(PLN * PLN));
+    for (; w < ntask; w += gridDim.x) {
+        plane_to_lds(pl, v);
+        lds_barrier();
+        const long long wn = w + gridDim.x;
+        if (wn < ntask) plane_load(v, in.field(wn / nz) + (wn % nz) * (long long)(PLN * PLN));
+        plane_lines<false, 0>(pl, twx);
+        plane_lines<false, 1>(pl, twy);
+        const long long f = w / nz;
+        const long long vec = f / 6;
+        const int s = (int)(f % 6);
+        const int so = s < 3 ? s + 3 : s - 3;
+        float2* dst = out.field(vec * 6 + so) + (w % nz) * (long long)(PLN * PLN);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = t + 1024 * j;
+            dst[e] = pl[(e >> 7) * PLP + (e & 127)];
+        }
+        lds_barrier();       // the plane is read out of LDS before the next one is staged
+    }
+}
+
+// inverse + coupling.  Task (g, a): group g = (plane z, vector, half h), h fastest and z
+// slowest, component a.  Workgroup b runs on XCD b % 8; each XCD takes a contiguous run of
+// groups and deals their tasks to its workgroups in order, so the three components of a
+// group (which read the same three input planes and coefficient rows) and the groups of one
+// plane (which read the same coefficient planes) run at about the same time on one XCD and
+// share its L2.
+template <int TRANS>
+__global__ void __launch_bounds__(1024) k_plane_inv_couple(FieldAddr<const float2> xin, FieldAddr<float2> yio,
+                                                           long long nvec, int nz, const float2* __restrict__ twx,
+                                                           const float2* __restrict__ twy,
+                                                           const float* __restrict__ coef) {
+    extern __shared__ float2 pl[];
+    const long long ngroups = nvec * 2 * nz;
+    const int nxcd = 8, xcd = blockIdx.x % nxcd;
+    const int nslot = (gridDim.x - xcd + nxcd - 1) / nxcd;   // workgroups on this XCD
+    const int slot = blockIdx.x / nxcd;
+    const long long g0 = ngroups * xcd / nxcd, g1 = ngroups * (xcd + 1) / nxcd;
+    const long long ntask = 3 * (g1 - g0);
+    long long u = slot;
+    if (u >= ntask) return;
+    const int t = threadIdx.x;
+    const long long npts = xin.npts;
+    struct Task {
+        int a, h;
+        long long z, vec;
+    };
+    auto task_of = [&](long long uu) {
+        const long long g = g0 + uu / 3;
+        Task k;
+        k.a = (int)(uu % 3);
+        k.h = (int)(g % 2);
+        k.vec = (g / 2) % nvec;
+        k.z = g / (2 * nvec);
+        return k;
+    };
+    auto plane_of = [&](const Task& k) -> float2* {
+        return yio.field(k.vec * 6 + 3 * k.h + k.a) + k.z * (long long)(PLN * PLN);
+    };
+    auto sidx = [](int r, int c2) {
+        const int lo = r < c2 ? r : c2, hi = r < c2 ? c2 : r;
+        return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+    };
+    float2 v[16];
+    plane_load(v, plane_of(task_of(u)));
+    for (; u < ntask; u += nslot) {
+        plane_to_lds(pl, v);
+        lds_barrier();
+        if (u + nslot < ntask) plane_load(v, plane_of(task_of(u + nslot)));
+        plane_lines<true, 1>(pl, twy);
+        plane_lines<true, 0>(pl, twx);
+        const Task k = task_of(u);
+        const int a = k.a, h = k.h;
+        const long long poff = k.z * (long long)(PLN * PLN);
+        float2* io = plane_of(k);
+        // output half 0 (y_f): H_- acting on g (input half 1); half 1 (y_g): H_+ on f (half 0);
+        // the transpose exchanges H_+ and H_-
+        const int hin = 1 - h;
+        const bool plus = (h == 1) != (TRANS != 0);
+        const float* cb = coef + (plus ? 0 : 6) * npts + poff;
+        const float* c0 = cb + sidx(a, 0) * npts;
+        const float* c1 = cb + sidx(a, 1) * npts;
+        const float* c2 = cb + sidx(a, 2) * npts;
+        const float2* x0 = xin.field(k.vec * 6 + 3 * hin + 0) + poff;
+        const float2* x1 = xin.field(k.vec * 6 + 3 * hin + 1) + poff;
+        const float2* x2 = xin.field(k.vec * 6 + 3 * hin + 2) + poff;
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const int e = t + 1024 * j;
+            const float2 kk = pl[(e >> 7) * PLP + (e & 127)];
+            const float m0 = c0[e], m1 = c1[e], m2 = c2[e];
+            const float2 u0 = x0[e], u1 = x1[e], u2 = x2[e];
+            float2 y;
+            y.x = kk.x + m0 * u0.x + m1 * u1.x + m2 * u2.x;
+            y.y = kk.y + m0 * u0.y + m1 * u1.y + m2 * u2.y;
+            io[e] = y;
+        }
+        lds_barrier();
     }
 }
 
@@ -517,10 +719,42 @@ bdg_status apply_impl(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y
     return BDG_OK;
 }
 
+// the three-pass (f, g) operator of complex64 128 x 128 x nz grids (see k_plane_fwd)
+template <int TRANS>
+bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAddr<float2> Y, MultSpec ms) {
+    static bool lds_set = false;
+    if (!lds_set) {
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)PLANE_LDS));
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple<0>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple<1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
+        lds_set = true;
+    }
+    const long long nf = 6LL * nvec;
+    const int nz = c->n[2];
+    const long long ntask = nf * nz;
+    const unsigned grid = (unsigned)std::min<long long>(ntask, c->ncu);
+    hipLaunchKernelGGL(k_plane_fwd, dim3(grid), dim3(1024), PLANE_LDS, c->stream, X, Y, nf, nz,
+                       (const float2*)c->tw32[0], (const float2*)c->tw32[1]);
+    BDG_TRY(hip_check(c, hipGetLastError(), "k_plane_fwd"));
+    BDG_TRY((run_strided<float2, false, 1>(c, Y, nf, 2, ms)));
+    const unsigned grid_inv = (unsigned)std::max<long long>(8, std::min<long long>(ntask, c->ncu));
+    hipLaunchKernelGGL(k_plane_inv_couple<TRANS>, dim3(grid_inv), dim3(1024), PLANE_LDS, c->stream, X, Y,
+                       (long long)nvec, nz, (const float2*)c->tw32[0], (const float2*)c->tw32[1],
+                       (const float*)c->coef32);
+    return hip_check(c, hipGetLastError(), "k_plane_inv_couple");
+}
+
 template <typename V, int FORM, int TRANS>
 bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y) {
     MultSpec ms = make_ms(c, 0, 0.0);
     const long long nf = 6LL * nvec;
+    if constexpr (std::is_same<V, float2>::value && FORM == 1) {
+        if (c->apply_planes && c->dim == 3 && c->n[0] == PLN && c->n[1] == PLN)
+            return apply_planes<TRANS>(c, nvec, X, Y, ms);
+    }
     if (c->dim == 1) return run_couple<V, FORM, TRANS, true>(c, X, Y, nvec, ms);
     BDG_TRY((run_xpass<V, false, 0>(c, X, Y, nf, ms)));
     if (c->dim == 2) {

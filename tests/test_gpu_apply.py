@@ -75,6 +75,49 @@ def test_apply_fp32_matches_oracle(w):
     ctx.close()
 
 
+PLANE_CASE = W.Workload("3d_128x128x8_fm", 3, (128, 128, 8), (8.0, 8.0, 2.0), "harmonic3_z2", 40.0, -0.5, 0.1)
+
+
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_apply_fp32_plane_passes_match_oracle(transpose, monkeypatch):
+    """complex64 (f, g) operator on a 128 x 128 x nz grid: the three-pass form (xy planes in
+    LDS) against the oracle, and against the five-pass form of the same context settings."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Form, Precision
+    w = PLANE_CASE
+    say(f"apply fp32 planes {w.name} T={transpose}")
+    # the operator alone is under test: the initial spinor of the flow serves as ground state
+    V = W.potential(w)
+    phi, mu = W.initial_spinor(w), np.array([1.0, 0.9, 1.1])
+    coef = bdg.coefficients(phi, mu, V, w.beta_n, w.beta_s)
+    X = W.random_block((5, 6) + w.shape, seed=9)
+    X32 = X.astype(np.complex64)
+    outs = []
+    for planes in ("1", "0"):
+        monkeypatch.setenv("BDG_APPLY_PLANES", planes)
+        ctx = make_ctx(w, Precision.FP32_APPLY, V)
+        ctx.set_ground_state(torch.from_numpy(phi), mu)
+        outs.append(ctx.apply(torch.from_numpy(X32).to("cuda"), Form.FG, bool(transpose)).cpu().numpy()
+                     .astype(np.complex128))
+        ctx.close()
+    Xr = X32.astype(np.complex128)
+    if transpose:
+        Hp, Hm = bdg.hpm(coef)
+        from oracle import spectral
+        f, g = Xr[:, :3], Xr[:, 3:]
+        ref = np.concatenate([spectral.kinetic_apply(g, w.n, w.L) + bdg._pw(Hp, g),
+                              spectral.kinetic_apply(f, w.n, w.L) + bdg._pw(Hm, f)], axis=1)
+    else:
+        ref = bdg.apply_fg(coef, Xr, w.n, w.L)
+    scale = np.abs(ref).max()
+    err = np.abs(outs[0] - ref).max() / scale
+    cross = np.abs(outs[0] - outs[1]).max() / scale
+    say(f"   rel err {err:.2e} (oracle), {cross:.2e} (five-pass form)")
+    assert err < 2e-6
+    assert cross < 2e-6
+    monkeypatch.delenv("BDG_APPLY_PLANES")
+
+
 def test_apply_rejects_bad_arguments():
     torch = torch_cuda()
     from paper_2506_08308_amd import BdgError, Form, Precision
