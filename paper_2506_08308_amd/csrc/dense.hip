@@ -296,43 +296,50 @@ __global__ void __launch_bounds__(256) k_gram_pair(long long K, int m1, int m2, 
             }
 }
 
-// Whole-matrix form of the symmetric paired Gram for 64 < m <= 128 complex columns (the
-// Rayleigh-Ritz Grams of a block of 33..64 complex columns): one workgroup of 8 waves holds
-// every upper block pair (bi <= bj, blocks of 16 complex columns) of its K-split, so each
-// input row is staged once per split instead of once per tile row and column, and the
-// arithmetic per staged byte doubles against the 64-column tiles.  Wave w takes a contiguous
-// run of the block pairs (at most WB = 5 of the 36), four accumulators (u, v) per pair.
+// Whole-matrix form of the paired Gram: one workgroup of 8 waves holds every block pair of
+// its K-split (blocks of 16 complex columns; symmetric: the upper pairs bi <= bj), so each
+// input row is staged once per split instead of once per tile row and column.  Taken for
+// symmetric Grams of 65..128 complex columns (the Rayleigh-Ritz Grams: 36 pairs) and for
+// general ones of at most 40 pairs within 128 x 128 (the F rows of the projected operators,
+// 3 x 8 pairs).  Wave w takes a contiguous run of the pairs (at most WB = 5), four
+// accumulators (u, v) per pair.
 constexpr int WGM = 128;        // columns staged per operand
 constexpr int WB = 5;           // block pairs per wave
-__global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m, SegList A, long long lda, SegList B,
-                                                        long long ldb, long long kper, int same,
-                                                        double* __restrict__ part) {
+__global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m1, int m2, int herm, SegList A,
+                                                        long long lda, SegList B, long long ldb, long long kper,
+                                                        int same, double* __restrict__ part) {
     __shared__ __align__(16) double la[WGM * GPAD];
     __shared__ __align__(16) double lb[WGM * GPAD];
     const long long split = blockIdx.x;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const long long ldr = 2LL * m;
-    double* out = part + split * ldr * ldr;
+    const long long ldr = 2LL * m1;
+    double* out = part + split * ldr * (2LL * m2);
     const double* lbr = same ? la : lb;
     const long long k0 = split * kper;
     long long k1 = k0 + kper;
     if (k1 > K) k1 = K;
-    // this wave's block pairs: npairs = nb (nb + 1) / 2 in row order, dealt out in runs
-    const int nb = (m + 15) / 16;
-    const int npairs = nb * (nb + 1) / 2;
+    // this wave's block pairs in row order, dealt out in runs
+    const int nb1 = (m1 + 15) / 16, nb2 = (m2 + 15) / 16;
+    const int npairs = herm ? nb1 * (nb1 + 1) / 2 : nb1 * nb2;
     const int base = npairs / 8, extra = npairs % 8;
     const int first = wave * base + (wave < extra ? wave : extra);
     const int cnt = base + (wave < extra ? 1 : 0);
     int bi[WB], bj[WB];
 #pragma unroll
     for (int j = 0; j < WB; ++j) {
-        int e = first + j, r = 0;
-        while (r < nb && e >= nb - r) {
-            e -= nb - r;
-            ++r;
+        int e = first + j;
+        if (herm) {
+            int r = 0;
+            while (r < nb1 && e >= nb1 - r) {
+                e -= nb1 - r;
+                ++r;
+            }
+            bi[j] = r;
+            bj[j] = r + e;
+        } else {
+            bi[j] = e / nb2;
+            bj[j] = e % nb2;
         }
-        bi[j] = r;
-        bj[j] = r + e;
     }
     d4 acc[WB][4];
 #pragma unroll
@@ -346,8 +353,8 @@ __global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m, SegL
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
         const int col = lc + 32 * pass;
-        acol[pass] = col < m ? seg_col(A, col, lda) : nullptr;
-        bcol[pass] = (!same && col < m) ? seg_col(B, col, ldb) : nullptr;
+        acol[pass] = col < m1 ? seg_col(A, col, lda) : nullptr;
+        bcol[pass] = (!same && col < m2) ? seg_col(B, col, ldb) : nullptr;
     }
     double2 ra[4], rb[4];
     auto gload = [&](long long kc) {
@@ -395,7 +402,7 @@ __global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m, SegL
         for (int r = 0; r < 4; ++r) {
             const int p = 16 * bi[j] + 4 * r + (lane >> 4);
             const int q = 16 * bj[j] + (lane & 15);
-            if (p < m && q < m) {
+            if (p < m1 && q < m2) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -1578,18 +1585,21 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
                       : 0;
     bool same = hermitian && na == nbs && lda == ldb;
     for (int i = 0; same && i < na; ++i) same = sa[i].p == sb[i].p && sa[i].ncols == sb[i].ncols;
-    if (hermitian && m1 > GT && m1 <= WGM && c->gram_wide) {
+    const int nb1 = (m1 + 15) / 16, nb2 = (m2 + 15) / 16;
+    const bool wide = c->gram_wide && m1 <= WGM && m2 <= WGM &&
+                      (hermitian ? m1 > GT : (m1 > 16 && nb1 * nb2 <= 8 * WB && nb1 * nb2 > 4));
+    if (wide) {
         // one workgroup per split covers the whole matrix: about two workgroups per CU
         long long nsplit = 1;
         const long long kper = gram_rows_per_split(K, 1, 2LL * c->ncu, &nsplit, max_split);
         void* ws = nullptr;
         BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * r1 * r2 * sizeof(double), &ws));
-        hipLaunchKernelGGL(k_gram_pair_wide, dim3((unsigned)nsplit), dim3(512), 0, c->stream, K, m1, A, lda, B, ldb,
-                           kper, same ? 1 : 0, (double*)ws);
+        hipLaunchKernelGGL(k_gram_pair_wide, dim3((unsigned)nsplit), dim3(512), 0, c->stream, K, m1, m2,
+                           hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
         BDG_HIP(c, hipGetLastError());
         const long long tot = r1 * r2;
         hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, (int)r1,
-                           (int)r2, (int)nsplit, (const double*)ws, alpha, C, ldc, 1);
+                           (int)r2, (int)nsplit, (const double*)ws, alpha, C, ldc, hermitian ? 1 : 0);
         return hip_check(c, hipGetLastError(), "k_gram_pair_wide");
     }
     const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;

@@ -203,10 +203,12 @@ def test_complete_pivoting_lu_biorthogonalizes(p, q, rank):
 # sym: 0 general, 1 B = A, 2 B = D A (the Rayleigh-Ritz shape S^T (H S) with symmetric H);
 # shapes reach single and several tiles, K-splits and ragged tails; symmetric forms of 65..128
 # complex columns take the whole-matrix kernel (one workgroup per K-split), 100 and 128 with
-# ragged K included.
+# ragged K included, and general ones of at most 40 block pairs (the F rows of the projected
+# operators).
 @pytest.mark.parametrize("K,m1,m2,sym", [(37, 5, 7, 0), (3072, 64, 64, 1), (20000, 120, 120, 2), (100000, 120, 120, 1),
                                          (5000, 40, 120, 0), (12, 65, 65, 1), (70001, 3, 16, 0), (9000, 36, 36, 2),
-                                         (50003, 100, 100, 2), (4099, 128, 128, 2), (777, 97, 97, 1)])
+                                         (50003, 100, 100, 2), (4099, 128, 128, 2), (777, 97, 97, 1),
+                                         (30011, 33, 100, 0), (2048, 80, 40, 0)])
 def test_gram_pair_matches_numpy(K, m1, m2, sym):
     torch = torch_cuda()
     from paper_2506_08308_amd import _lib
