@@ -1083,8 +1083,6 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
     constexpr int N2 = 2 * W, PA = N2 + 1, TPC = 256 / N2, U = 8;
     static_assert(256 % N2 == 0, "columns divide the workgroup");
     extern __shared__ double smr[];
-    __shared__ double prm[W][3];
-    __shared__ int pact[W];
     __shared__ int rot_any;
     const int t = threadIdx.x;
     auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (nblk - 1)) + 1; };
@@ -1151,30 +1149,26 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
         auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (N2 - 1)) + 1; };
         int p = pl(pair), q = pl(N2 - 1 - pair);
         if (p > q) { const int tmp = p; p = q; q = tmp; }
-        if (sub == 0) {
-            int act = 0;
-            if (valid(p) && valid(q)) {
-                const double al = A[p * PA + p], be = A[q * PA + q];
-                const double gm = A[q * PA + p];
-                const double g = fabs(gm);
-                if (g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
-                    if (g > conv * sqrt(al * be)) rot_any = 1;
-                    const double zeta = (be - al) / (2.0 * g);
-                    const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
-                                                         : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt);
-                    prm[pair][0] = cs;
-                    prm[pair][1] = cs * tt;
-                    prm[pair][2] = gm >= 0.0 ? 1.0 : -1.0;    // e = sign(gamma)
-                    act = 1;
-                }
-            }
-            pact[pair] = act;
-        }
-        __syncthreads();
-        const bool act = pact[pair];
+        // every thread of the pair computes the rotation itself (same inputs, same result), so
+        // no barrier separates the parameters from the updates
+        bool act = false;
         double cs = 0, sn = 0, ex = 0;
-        if (act) { cs = prm[pair][0]; sn = prm[pair][1]; ex = prm[pair][2]; }
+        if (valid(p) && valid(q)) {
+            const double al = A[p * PA + p], be = A[q * PA + q];
+            const double gm = A[q * PA + p];
+            const double g = fabs(gm);
+            const double sab = sqrt(al * be);
+            if (g > tol * sab && g > 0.0 && al > negl && be > negl) {
+                if (g > conv * sab && sub == 0) rot_any = 1;
+                const double zeta = (be - al) / (2.0 * g);
+                const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
+                                                     : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                cs = 1.0 / sqrt(1.0 + tt * tt);
+                sn = cs * tt;
+                ex = gm >= 0.0 ? 1.0 : -1.0;    // e = sign(gamma)
+                act = true;
+            }
+        }
         if (act) {
             // columns p, q of A and J: [a, b] <- [cs a - sn e b, sn a + cs e b]
             for (int i = sub; i < N2; i += tpp) {
@@ -1198,22 +1192,44 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
         }
         __syncthreads();
     }
-    // [G; V] columns <- [G; V] columns J (each thread owns whole rows)
-    for (int i = t; i < rows + m; i += 256) {
-        const bool isg = i < rows;
-        const int ii = isg ? i : i - rows;
-        double x[N2];
+    // [G; V] columns <- [G; V] columns J on the FP64 matrix cores: the rows + m rows in blocks
+    // of 16 (G rows from LDS, V rows from memory), D = X J over N2 / 4 steps of four columns
+    // of X; register r of lane l holds D[4 r + l / 16][l % 16], a lane's A operand is
+    // X[l % 16][l / 16] and its B operand J[l / 16][l % 16] of the step
+    {
+        const int wave = t >> 6, lane = t & 63;
+        const int li = lane & 15, lk = lane >> 4;
+        const int nrb = (rows + m + 15) / 16;
+        for (int rb = wave; rb < nrb; rb += 4) {
+            const int row = 16 * rb + li;                  // this lane's A row
+            const bool rg = row < rows;
+            const bool rv = !rg && row < rows + m;
+            d4 acc[N2 / 16 > 0 ? N2 / 16 : 1];
 #pragma unroll
-        for (int k = 0; k < N2; ++k)
-            x[k] = isg ? lg[k * pg + ii] : (valid(k) ? V[(long long)colidx(k) * ldv + ii].x : 0.0);
+            for (int cb = 0; cb < (N2 + 15) / 16; ++cb) acc[cb] = d4{0, 0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < N2; ++c) {
-            if (!valid(c)) continue;
-            double sx = 0;
+            for (int kc = 0; kc < N2 / 4; ++kc) {
+                const int kk = 4 * kc + lk;
+                const double a = rg ? lg[kk * pg + row]
+                                    : ((rv && valid(kk)) ? V[(long long)colidx(kk) * ldv + (row - rows)].x : 0.0);
 #pragma unroll
-            for (int k = 0; k < N2; ++k) sx += x[k] * J[c * PA + k];
-            if (isg) G[(long long)colidx(c) * ldg + ii] = mkc(sx, 0.0);
-            else V[(long long)colidx(c) * ldv + ii] = mkc(sx, 0.0);
+                for (int cb = 0; cb < (N2 + 15) / 16; ++cb) {
+                    const int cc = 16 * cb + li;
+                    const double b = cc < N2 ? J[cc * PA + kk] : 0.0;
+                    acc[cb] = mfma(a, b, acc[cb]);
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < (N2 + 15) / 16; ++cb) {
+                const int cc = 16 * cb + li;
+                if (cc >= N2 || !valid(cc)) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int orow = 16 * rb + 4 * r + lk;
+                    if (orow < rows) G[(long long)colidx(cc) * ldg + orow] = mkc(acc[cb][r], 0.0);
+                    else if (orow < rows + m) V[(long long)colidx(cc) * ldv + (orow - rows)] = mkc(acc[cb][r], 0.0);
+                }
+            }
         }
     }
     if (t == 0 && rot_any) atomicAdd(rotations, 1);
