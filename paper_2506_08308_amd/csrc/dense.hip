@@ -413,16 +413,16 @@ __global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m1, int
 }
 
 // C (m1 x m2 real entries in complex storage, imaginary parts 0) = alpha * sum over the splits
-// of the real partials, in split order; herm mirrors every entry below the diagonal 16 x 16
-// blocks from above (the paired tiles compute those blocks, see k_gram_pair)
+// of the real partials, in split order.  herm: only the entries on or above the diagonal
+// 16 x 16 blocks are read (in their own column order, so a wave's reads are contiguous) and
+// each is written to C and to its mirror; the paired kernels compute at least those blocks.
 __global__ void k_gram_reduce_real(int m1, int m2, int nsplit, const double* __restrict__ part, double alpha,
                                    double2* __restrict__ C, int ldc, int herm) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)m1 * m2) return;
     const int p = (int)(idx % m1), q = (int)(idx / m1);
-    const bool mirror = herm && (p / 16) > (q / 16);
-    const int ps = mirror ? q : p, qs = mirror ? p : q;
-    const long long plane = (long long)m1 * m2, off = (long long)qs * m1 + ps;
+    if (herm && (p / 16) > (q / 16)) return;
+    const long long plane = (long long)m1 * m2, off = (long long)q * m1 + p;
     double sx = 0;
     int s = 0;
     for (; s + 8 <= nsplit; s += 8) {
@@ -434,6 +434,7 @@ __global__ void k_gram_reduce_real(int m1, int m2, int nsplit, const double* __r
     }
     for (; s < nsplit; ++s) sx += part[s * plane + off];
     C[(long long)q * ldc + p] = double2{alpha * sx, 0.0};
+    if (herm && (p / 16) < (q / 16)) C[(long long)p * ldc + q] = double2{alpha * sx, 0.0};
 }
 
 // Tiles of Q x Q blocks of 16 x 16 (k_gram80: Q = 5) on 2 Q waves.  Wave w computes the real
