@@ -41,6 +41,13 @@ bdg_status bdg_test_update_pair(bdg_ctx* ctx, long long K, int m, const void* S,
 
 /* One-sided Jacobi SVD of G (rows x m, ldg), m <= 512: G is replaced by U diag(s) with
  * columns ordered by descending s; V (m x m, ldv) receives V; s (device, m). */
+/* One-pass form of the paired update the eigensolver uses for blocks of up to 96 real columns:
+ * S (K x m complex columns, lds; the first mF of them F, mF a multiple of 8), Cm as in
+ * bdg_test_update_pair (2 m x nb real coefficients in complex storage, ldcm >= 2 m):
+ * Yp = S[:, mF:] Cm[2 mF:, :] and Yf = S[:, :mF] Cm[:2 mF, :] + Yp (nb even, <= 96 real
+ * columns, both K x nb / 2 complex, ld ldy). */
+bdg_status bdg_test_update_pair_fused(bdg_ctx* ctx, long long K, int m, int mF, const void* S, long long lds,
+                                      const void* Cm, int ldcm, int nb, void* Yp, void* Yf, long long ldy);
 bdg_status bdg_test_svd(bdg_ctx* ctx, int rows, int m, void* G, int ldg, void* V, int ldv, void* s);
 /* The same for a real G held in complex storage (imaginary parts zero; the projected
  * matrices of the paired real form): real rotations, V real. */

@@ -463,6 +463,18 @@ bdg_status bdg_test_update_pair(bdg_ctx* c, long long K, int m, const void* S, l
     return BDG_OK;
 }
 
+bdg_status bdg_test_update_pair_fused(bdg_ctx* c, long long K, int m, int mF, const void* S, long long lds,
+                                      const void* Cm, int ldcm, int nb, void* Yp, void* Yf, long long ldy) {
+    if (!c || !S || !Cm || !Yp || !Yf || K < 1 || m < 1 || nb < 2 || (nb & 1) || nb > 96 || mF < 0 || mF > m ||
+        mF % 8 != 0 || ldcm < 2 * m || ldy < K)
+        return ctx_fail(c, BDG_EINVAL, "bad args");
+    Seg s{S, m};
+    BDG_TRY(update_pair_fused(c, K, &s, 1, lds, (const double2*)Cm, ldcm, nb, mF, (double2*)Yp, ldy, (double2*)Yf,
+                              ldy));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+
 bdg_status bdg_test_svd(bdg_ctx* c, int rows, int m, void* G, int ldg, void* V, int ldv, void* s) {
     if (!c || !G || !V || !s || m < 1 || m > 512 || rows < 1 || ldg < rows || ldv < m)
         return ctx_fail(c, BDG_EINVAL, "bad args");

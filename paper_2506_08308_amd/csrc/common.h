@@ -196,6 +196,11 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
 // 2 mp x nbr coefficient matrix Cr, ld ldcr, from row r0) + beta Z; nbr even; Y must not overlap S
 bdg_status update_pair(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cr, int ldcr,
                        int r0, int nbr, double beta, const double2* Z, long long ldz, double2* Y, long long ldy);
+// Y_p (nbr real columns) = S[mF:] Cr[2 mF :, :] and Y_f = S[:mF] Cr[: 2 mF, :] + Y_p in one pass
+// (S: segments of mp complex columns, the first mF of them F; Cr as in update_pair from row 0).
+// nbr even and <= 96, mF a multiple of 8.  Y_f may alias the rows of an input (row-local).
+bdg_status update_pair_fused(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cr,
+                             int ldcr, int nbr, int mF, double2* Yp, long long ldyp, double2* Yf, long long ldyf);
 // squared norms of the 2 ncols real columns of ncols complex columns
 bdg_status colnorm2_pair(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx, double* out_dev);
 // residual norms of the 2 ncols real columns (omega per real column, om_dev[2 ncols]):

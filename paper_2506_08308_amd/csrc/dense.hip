@@ -698,10 +698,16 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
 // 2 x 2 coefficient block as two double2 at Cm[j ldcm + 2 l] = (c00, c01) and
 // Cm[j ldcm + 2 l + 1] = (c10, c11) with c_uv the coefficient of real column 2 l + u of S in
 // real column 2 j + v of Y; Y.x += S.x c00 + S.y c10, Y.y += S.x c01 + S.y c11.
-template <int CB, int RA, bool PAIR>
+// FUSE (paired form): the first mF columns of S are F, the rest [W, P]; the kernel writes
+// Y2 = [W, P] C[mF:] (P_new) and Y = F C[:mF] + Y2 (F_new) in one pass with one set of
+// accumulators: it visits the [W, P] chunks first, stores Y2 from the accumulators, and goes
+// on with the F chunks.  Y may alias an input of the same rows: a workgroup reads all its
+// input rows before it writes its output rows, and owns all output columns of its rows.
+template <int CB, int RA, bool PAIR, bool FUSE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(long long K, SegList segs, long long lds, int m,
                                                 const double2* __restrict__ Cm, int ldcm, int nb, double beta,
-                                                const double2* Z, long long ldz, double2* Y, long long ldy) {
+                                                const double2* Z, long long ldz, double2* Y, long long ldy,
+                                                int mF, double2* Y2, long long ldy2) {
     // a workgroup owns RW = 64 RA rows (each wave 16 RA rows) and 16 CB columns; LDS chunks of
     // UL columns of S and UL rows of Cm (2 UL for the paired form), the next chunk held in
     // registers while the MFMAs of the current one run
@@ -722,16 +728,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < CB; ++b) { accr[a][b] = d4{0, 0, 0, 0}; acci[a][b] = d4{0, 0, 0, 0}; }
+    // chunk order: FUSE visits [mF, m) first (nwp chunks), then [0, mF); the plain form [0, m)
+    const int nwp = FUSE ? (m - mF + UL - 1) / UL : 0;
+    const int nchunk = FUSE ? nwp + mF / UL : (m + UL - 1) / UL;
+    auto chunk_start = [&](int it) { return FUSE ? (it < nwp ? mF + it * UL : (it - nwp) * UL) : it * UL; };
+    auto chunk_end = [&](int it) { return FUSE ? (it < nwp ? m : mF) : m; };
     constexpr int SPASS = UL * RW / 256;
     constexpr int CPASS = (CR * NC + 255) / 256;
     double2 rs[SPASS], rc[CPASS];
-    auto gload = [&](int l0) {
+    auto gload = [&](int l0, int lend) {
 #pragma unroll
         for (int u = 0; u < SPASS; ++u) {
             const int idx = u * 256 + t;
             const int l = l0 + idx / RW, row = idx % RW;
             rs[u] = double2{0, 0};
-            if (l < m && R0 + row < K) rs[u] = seg_col(segs, l, lds)[R0 + row];
+            if (l < lend && R0 + row < K) rs[u] = seg_col(segs, l, lds)[R0 + row];
         }
 #pragma unroll
         for (int u = 0; u < CPASS; ++u) {
@@ -740,11 +751,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             rc[u] = double2{0, 0};
             const int lc = PAIR ? l0 + l / 2 : l0 + l;
             const int row = PAIR ? 2 * l0 + l : l0 + l;
-            if (idx < CR * NC && lc < m && j0 + j < nb) rc[u] = Cm[(long long)(j0 + j) * ldcm + row];
+            if (idx < CR * NC && lc < lend && j0 + j < nb) rc[u] = Cm[(long long)(j0 + j) * ldcm + row];
         }
     };
-    gload(0);
-    for (int l0 = 0; l0 < m; l0 += UL) {
+    // accumulators -> Yo (plus beta Z in the plain form)
+    auto store = [&](double2* Yo, long long ldo, bool with_z) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const int j = j0 + 16 * b + (lane & 15);
+                if (j >= nb) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const long long row = R0 + wr + 16 * a + 4 * r + (lane >> 4);
+                    if (row >= K) continue;
+                    double2 v;
+                    v.x = accr[a][b][r];
+                    v.y = acci[a][b][r];
+                    if (with_z && beta != 0.0) {
+                        const double2 o = Z[(long long)j * ldz + row];
+                        v.x += beta * o.x;
+                        v.y += beta * o.y;
+                    }
+                    Yo[(long long)j * ldo + row] = v;
+                }
+            }
+    };
+    if (FUSE && nwp == 0) store(Y2, ldy2, false);    // no [W, P] part: P_new = 0
+    if (nchunk > 0) gload(chunk_start(0), chunk_end(0));
+    for (int it = 0; it < nchunk; ++it) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < SPASS; ++u) {
@@ -757,7 +793,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             if (idx < CR * NC) lsC[(idx % CR) * NC + idx / CR] = rc[u];
         }
         __syncthreads();
-        if (l0 + UL < m) gload(l0 + UL);
+        if (it + 1 < nchunk) gload(chunk_start(it + 1), chunk_end(it + 1));
 #pragma unroll
         for (int ks = 0; ks < UL; ks += 4) {
             const int l = ks + kq;
@@ -792,28 +828,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     acci[a][b] = mfma(sv[a].y, cw[b].y, acci[a][b]);
                 }
         }
+        if (FUSE && it == nwp - 1) store(Y2, ldy2, false);   // P_new; F's chunks follow
     }
-#pragma unroll
-    for (int a = 0; a < RA; ++a)
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int j = j0 + 16 * b + (lane & 15);
-            if (j >= nb) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const long long row = R0 + wr + 16 * a + 4 * r + (lane >> 4);
-                if (row >= K) continue;
-                double2 v;
-                v.x = accr[a][b][r];
-                v.y = acci[a][b][r];
-                if (beta != 0.0) {
-                    const double2 o = Z[(long long)j * ldz + row];
-                    v.x += beta * o.x;
-                    v.y += beta * o.y;
-                }
-                Y[(long long)j * ldy + row] = v;
-            }
-        }
+    store(Y, ldy, !FUSE);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1576,7 +1593,8 @@ bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long l
     constexpr int RA = 1;
     dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), (unsigned)ctiles);
 #define BDG_UPD(CBV) \
-    hipLaunchKernelGGL((k_update<CBV, RA, false>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy)
+    hipLaunchKernelGGL((k_update<CBV, RA, false>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy, \
+                       0, (double2*)nullptr, 0LL)
     switch (cb) {
         case 1: BDG_UPD(1); break;
         case 2: BDG_UPD(2); break;
@@ -1657,7 +1675,7 @@ bdg_status update_pair(bdg_ctx* c, long long K, const Seg* segs, int nseg, long 
     dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), (unsigned)ctiles);
 #define BDG_UPDP(CBV) \
     hipLaunchKernelGGL((k_update<CBV, RA, true>), grid, dim3(256), 0, c->stream, K, sl, lds, mp, (const double2*)Cp, \
-                       2 * mp, nbp, beta, Z, ldz, Y, ldy)
+                       2 * mp, nbp, beta, Z, ldz, Y, ldy, 0, (double2*)nullptr, 0LL)
     switch (cb) {
         case 1: BDG_UPDP(1); break;
         case 2: BDG_UPDP(2); break;
@@ -1667,6 +1685,37 @@ bdg_status update_pair(bdg_ctx* c, long long K, const Seg* segs, int nseg, long 
     }
 #undef BDG_UPDP
     return hip_check(c, hipGetLastError(), "k_update_pair");
+}
+
+bdg_status update_pair_fused(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cr,
+                             int ldcr, int nbr, int mF, double2* Yp, long long ldyp, double2* Yf, long long ldyf) {
+    if (nbr <= 0 || K <= 0) return BDG_OK;
+    if ((nbr & 1) || nbr > 96 || mF % 8 != 0) return ctx_fail(c, BDG_EINVAL, "update_pair_fused: unsupported shape");
+    SegList sl;
+    int mp = 0;
+    if (!make_seglist(segs, nseg, &sl, &mp)) return ctx_fail(c, BDG_EINVAL, "update: 1..4 segments");
+    if (mF < 0 || mF > mp) return ctx_fail(c, BDG_EINVAL, "update_pair_fused: F columns out of range");
+    const int nbp = nbr / 2;
+    void* ws = nullptr;
+    BDG_TRY(ctx_scratch(c, 7, (size_t)2 * mp * nbp * sizeof(double2), &ws));
+    double2* Cp = (double2*)ws;
+    hipLaunchKernelGGL(k_pack_pair_coef, dim3((unsigned)((mp + 127) / 128), (unsigned)nbp), dim3(128), 0, c->stream,
+                       mp, nbp, Cr, ldcr, 0, Cp);
+    BDG_HIP(c, hipGetLastError());
+    // one column tile (CB <= 3 covers nbp <= 48): a workgroup owns all output columns of its rows
+    const int cb = (nbp + 15) / 16;
+    constexpr int RA = 1;
+    dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), 1);
+#define BDG_UPDF(CBV)                                                                                              \
+    hipLaunchKernelGGL((k_update<CBV, RA, true, true>), grid, dim3(256), 0, c->stream, K, sl, lds, mp,             \
+                       (const double2*)Cp, 2 * mp, nbp, 0.0, (const double2*)nullptr, 0LL, Yf, ldyf, mF, Yp, ldyp)
+    switch (cb) {
+        case 1: BDG_UPDF(1); break;
+        case 2: BDG_UPDF(2); break;
+        default: BDG_UPDF(3); break;
+    }
+#undef BDG_UPDF
+    return hip_check(c, hipGetLastError(), "k_update_pair_fused");
 }
 
 bdg_status colnorm2_pair(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx, double* out_dev) {

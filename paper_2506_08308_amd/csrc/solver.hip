@@ -60,6 +60,15 @@ bool debug_on() {
     return v == 1;
 }
 
+// BDG_UPDATE_FUSE=0 takes the two-launch basis update
+bool update_fuse_enabled() {
+    static const int v = [] {
+        const char* e = std::getenv("BDG_UPDATE_FUSE");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    return v == 1;
+}
+
 // runs a callable when the scope ends (workspace release on every return path)
 template <typename Fn> struct Defer {
     Fn fn;
@@ -1115,9 +1124,14 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
                 if (rmax < best_r * 0.5) { best_r = rmax; best_it = it; }
                 if (it - best_it > opt.stall_iters || rmax > opt.rise_factor * best_r) {
                     switch64 = true;
-                    if (debug_on())
+                    if (debug_on()) {
                         fprintf(stderr, "[bdg it %d] float64 applies from here: residual %.3e, best %.3e at it %d\n",
                                 it, rmax, best_r, best_it);
+                        for (int j = 0; j < k; ++j)
+                            if (res[j] > 4.0 * best_r)
+                                fprintf(stderr, "[bdg it %d]   column %d omega %.12f residual %.3e\n", it, j, om[j],
+                                        res[j]);
+                    }
                 }
             }
         }
@@ -1295,19 +1309,27 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         }
         if (rst != BDG_OK) { final_status = rst; break; }
         BDG_TRY(mark(4));
-        // updates: P_new = [W, P] a[nb:] into the free slot, then F_new = F a[:nb] + P_new
-        // into W's slot (W is no longer read), so no output overlaps an input
+        // updates: P_new = [W, P] a[nb:] into the free slot and F_new = F a[:nb] + P_new into
+        // W's slot.  With float64 images, blocks of up to 96 real columns take one fused
+        // launch per array, which reads F, W and P once and writes both (F_new over W's rows
+        // is row-local); otherwise two launches, P_new first, so that no output overlaps an
+        // input.  The float32 phase keeps the two launches: the two forms differ in rounding
+        // order only, and that phase is sensitive to it (measured on the 3-D trap, the one-pass
+        // form's trajectory left the float32 phase at iteration 41 instead of 80)
         const int dst_P = S.slotFree, dst_F = S.slotW;
+        const bool fuse = nb <= 96 && nbc % 8 == 0 && !w32img && update_fuse_enabled();
         for (int a = 0; a < 4; ++a) {
             const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
             const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
-            BDG_TRY(update_pair(c, nh, seg + 1, ns - 1, nh, coef, mc, nb, nb, 0.0, S.col(a, dst_P), nh,
-                                S.col(a, dst_P), nh));
-        }
-        for (int a = 0; a < 4; ++a) {
-            const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
-            const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
-            BDG_TRY(update_pair(c, nh, seg, 1, nh, coef, mc, 0, nb, 1.0, S.col(a, dst_P), nh, S.col(a, dst_F), nh));
+            if (fuse) {
+                BDG_TRY(update_pair_fused(c, nh, seg, ns, nh, coef, mc, nb, nbc, S.col(a, dst_P), nh, S.col(a, dst_F),
+                                          nh));
+            } else {
+                BDG_TRY(update_pair(c, nh, seg + 1, ns - 1, nh, coef, mc, nb, nb, 0.0, S.col(a, dst_P), nh,
+                                    S.col(a, dst_P), nh));
+                BDG_TRY(update_pair(c, nh, seg, 1, nh, coef, mc, 0, nb, 1.0, S.col(a, dst_P), nh, S.col(a, dst_F),
+                                    nh));
+            }
         }
         // rotate slot roles
         const int oldF = S.slotF, oldP = S.slotP;

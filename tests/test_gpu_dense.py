@@ -238,6 +238,41 @@ def test_gram_pair_matches_numpy(K, m1, m2, sym):
     ctx.close()
 
 
+# One-pass update of the eigensolver (F columns first): the solve's shape, a ragged row tail,
+# no F part, no [W, P] part, and the widest block it takes (96 real columns)
+@pytest.mark.parametrize("K,m,mF,nb", [(5000, 120, 40, 80), (777, 24, 8, 16), (300, 16, 0, 10), (513, 16, 16, 6),
+                                       (100003, 72, 24, 96)])
+def test_update_pair_fused_matches_numpy(K, m, mF, nb):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"update pair fused K={K} m={m} mF={mF} nb={nb}")
+    ctx = _ctx()
+    S = W.random_block((m, K), seed=13)
+    Cr = np.random.default_rng(14).standard_normal((nb, 2 * m))    # column-major 2 m x nb, real
+    Sd = torch.from_numpy(S).cuda()
+    Cd = torch.from_numpy((Cr + 0.0j).astype(np.complex128)).cuda()
+    Yp = torch.full((nb // 2, K), 7.0 + 7.0j, dtype=torch.complex128, device="cuda")
+    Yf = torch.full((nb // 2, K), 7.0 + 7.0j, dtype=torch.complex128, device="cuda")
+    st = ctx._lib.bdg_test_update_pair_fused(ctx._h, K, m, mF, _p(Sd), K, _p(Cd), 2 * m, nb, _p(Yp), _p(Yf), K)
+    assert st == _lib.BDG_OK
+    Sr = np.stack([S.real, S.imag], axis=1).reshape(2 * m, K)
+    ref_p = Cr[:, 2 * mF:] @ Sr[2 * mF:]
+    ref_f = Cr[:, :2 * mF] @ Sr[:2 * mF] + ref_p
+    scale = max(np.abs(ref_f).max(), np.abs(ref_p).max())
+    for got, ref in ((Yp, ref_p), (Yf, ref_f)):
+        g = got.cpu().numpy()
+        g_r = np.stack([g.real, g.imag], axis=1).reshape(nb, K)
+        err = np.abs(g_r - ref).max() / scale
+        say(f"   rel err {err:.2e}")
+        assert err < 1e-13
+    # unsupported shapes are rejected (odd or too wide blocks, F not a multiple of 8)
+    assert ctx._lib.bdg_test_update_pair_fused(ctx._h, K, m, mF, _p(Sd), K, _p(Cd), 2 * m, 98, _p(Yp), _p(Yf),
+                                               K) == _lib.BDG_EINVAL
+    assert ctx._lib.bdg_test_update_pair_fused(ctx._h, K, m, 3, _p(Sd), K, _p(Cd), 2 * m, nb, _p(Yp), _p(Yf),
+                                               K) == _lib.BDG_EINVAL
+    ctx.close()
+
+
 @pytest.mark.parametrize("K,m,nb,beta", [(37, 5, 4, 0.0), (1000, 20, 16, 0.0), (5000, 120, 80, 1.0),
                                          (129, 7, 34, -0.5), (100000, 12, 8, 0.0)])
 def test_update_pair_matches_numpy(K, m, nb, beta):
