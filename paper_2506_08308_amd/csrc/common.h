@@ -80,6 +80,7 @@ struct bdg_ctx {
     bool apply_planes = true;
     // symmetric paired Grams of 65..128 complex columns by one workgroup per K-split
     bool gram_wide = true;
+    bool gram_w8 = true;          // ... in blocks of 8 complex columns
     // scratch owned by the context (grown on demand)
     DevBuf scratch[8];
     // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out

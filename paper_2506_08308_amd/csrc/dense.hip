@@ -412,6 +412,114 @@ __global__ void __launch_bounds__(512) k_gram_pair_wide(long long K, int m1, int
     }
 }
 
+// Whole-matrix paired Gram with blocks of 8 complex columns (16 real): one 16 x 16 MFMA tile
+// per block pair, so 120 complex columns need no padding and a diagonal tile wastes only its
+// lower half (the 16-column blocks padded 120 to 128 and computed full 32 x 32 diagonal
+// blocks: 22 % of their MFMAs).  A lane's A operand is one part of one complex column: real
+// row r of block bi is part r % 2 of complex column 8 bi + r / 2.  One workgroup of 16 waves
+// per K-split holds all tiles (symmetric: bi <= bj), at most W8T per wave.
+constexpr int W8T = 9;
+__global__ void __launch_bounds__(1024) k_gram_pair_w8(long long K, int m1, int m2, int herm, SegList A, long long lda,
+                                                      SegList B, long long ldb, long long kper, int same,
+                                                      double* __restrict__ part) {
+    __shared__ __align__(16) double la[WGM * GPAD];
+    __shared__ __align__(16) double lb[WGM * GPAD];
+    const long long split = blockIdx.x;
+    // the wave index (and all tile indices derived from it) is uniform: scalar registers
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const long long ldr = 2LL * m1;
+    double* out = part + split * ldr * (2LL * m2);
+    const double* lbr = same ? la : lb;
+    const long long k0 = split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const int nb1 = (m1 + 7) / 8, nb2 = (m2 + 7) / 8;
+    const int ntile = herm ? nb1 * (nb1 + 1) / 2 : nb1 * nb2;
+    const int base = ntile / 16, extra = ntile % 16;
+    const int first = wave * base + (wave < extra ? wave : extra);
+    const int cnt = base + (wave < extra ? 1 : 0);
+    int bi[W8T], bj[W8T];
+#pragma unroll
+    for (int j = 0; j < W8T; ++j) {
+        int e = first + j;
+        if (herm) {
+            int r = 0;
+            while (r < nb1 && e >= nb1 - r) {
+                e -= nb1 - r;
+                ++r;
+            }
+            bi[j] = r;
+            bj[j] = r + e;
+        } else {
+            bi[j] = e / nb2;
+            bj[j] = e % nb2;
+        }
+    }
+    d4 acc[W8T];
+#pragma unroll
+    for (int j = 0; j < W8T; ++j) acc[j] = d4{0, 0, 0, 0};
+    // staging: thread t loads complex row lk of columns lc + 64 pass (pass < 2) of A and B
+    const int lk = t & 15, lc = t >> 4;
+    const double2* acol[2];
+    const double2* bcol[2];
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const int col = lc + 64 * pass;
+        acol[pass] = col < m1 ? seg_col(A, col, lda) : nullptr;
+        bcol[pass] = (!same && col < m2) ? seg_col(B, col, ldb) : nullptr;
+    }
+    double2 ra[2], rb[2];
+    auto gload = [&](long long kc) {
+        const long long kk = kc + lk;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            ra[pass] = (kk < k1 && acol[pass]) ? acol[pass][kk] : double2{0, 0};
+            rb[pass] = (kk < k1 && bcol[pass]) ? bcol[pass][kk] : double2{0, 0};
+        }
+    };
+    // this lane's operand offsets within a block: column (lane % 16) / 2, part lane % 2,
+    // complex row lane / 16 of the four of a step
+    const int ci = (lane & 15) >> 1, cu = lane & 1, kq = lane >> 4;
+    gload(k0);
+    for (long long kc = k0; kc < k1; kc += GKC) {
+        __syncthreads();
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int col = lc + 64 * pass;
+            *reinterpret_cast<double2*>(&la[col * GPAD + 2 * lk]) = ra[pass];
+            if (!same) *reinterpret_cast<double2*>(&lb[col * GPAD + 2 * lk]) = rb[pass];
+        }
+        __syncthreads();
+        if (kc + GKC < k1) gload(kc + GKC);
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < GKC; ks += 4) {
+            const int kr = 2 * (ks + kq) + cu;
+#pragma unroll
+            for (int j = 0; j < W8T; ++j) {
+                if (j < cnt) {            // wave-uniform
+                    const double av = la[(8 * bi[j] + ci) * GPAD + kr];
+                    const double bv = lbr[(8 * bj[j] + ci) * GPAD + kr];
+                    acc[j] = mfma(av, bv, acc[j]);
+                }
+            }
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+    // register r of lane l holds D[4 r + l / 16][l % 16]: real row 16 bi + 4 r + l / 16,
+    // real column 16 bj + l % 16
+#pragma unroll
+    for (int j = 0; j < W8T; ++j) {
+        if (j >= cnt) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * bi[j] + 4 * r + (lane >> 4);
+            const int q = 16 * bj[j] + (lane & 15);
+            if (p < 2 * m1 && q < 2 * m2) out[(long long)q * ldr + p] = acc[j][r];
+        }
+    }
+}
+
 // C (m1 x m2 real entries in complex storage, imaginary parts 0) = alpha * sum over the splits
 // of the real partials, in split order.  herm: only the entries on or above the diagonal
 // 16 x 16 blocks are read (in their own column order, so a wave's reads are contiguous) and
@@ -1623,14 +1731,20 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
     const int nb1 = (m1 + 15) / 16, nb2 = (m2 + 15) / 16;
     const bool wide = c->gram_wide && m1 <= WGM && m2 <= WGM &&
                       (hermitian ? m1 > GT : (m1 > 16 && nb1 * nb2 <= 8 * WB && nb1 * nb2 > 4));
+    const int t1 = (m1 + 7) / 8, t2 = (m2 + 7) / 8;
+    const bool w8 = wide && c->gram_w8 && (hermitian ? t1 * (t1 + 1) / 2 : t1 * t2) <= 16 * W8T;
     if (wide) {
         // one workgroup per split covers the whole matrix: about two workgroups per CU
         long long nsplit = 1;
         const long long kper = gram_rows_per_split(K, 1, 2LL * c->ncu, &nsplit, max_split);
         void* ws = nullptr;
         BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * r1 * r2 * sizeof(double), &ws));
-        hipLaunchKernelGGL(k_gram_pair_wide, dim3((unsigned)nsplit), dim3(512), 0, c->stream, K, m1, m2,
-                           hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
+        if (w8)
+            hipLaunchKernelGGL(k_gram_pair_w8, dim3((unsigned)nsplit), dim3(1024), 0, c->stream, K, m1, m2,
+                               hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
+        else
+            hipLaunchKernelGGL(k_gram_pair_wide, dim3((unsigned)nsplit), dim3(512), 0, c->stream, K, m1, m2,
+                               hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
         BDG_HIP(c, hipGetLastError());
         const long long tot = r1 * r2;
         hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, (int)r1,
