@@ -1,8 +1,8 @@
-// Dense linear algebra of the subspace iteration on gfx950 (Section 3.2): the Gram
+// Tall-skinny linear algebra of the subspace iteration on gfx950 (Section 3.2): the Gram
 // matrices X^H Y of the bi-orthogonal Gram-Schmidt and Rayleigh-Ritz steps and the basis
-// updates S C run on the FP64 matrix cores (v_mfma_f64_16x16x4f64); the small projected
-// problems (m <= 512) use single-workgroup FP64 kernels (Cholesky, one-sided Jacobi SVD)
-// and a plain small GEMM.  Complex numbers are interleaved (re, im) doubles.
+// updates S C run on the FP64 matrix cores (v_mfma_f64_16x16x4f64), with the column norms
+// and dot products of the block.  The projected m x m problems are in smalldense.hip.
+// Complex numbers are interleaved (re, im) doubles.
 //
 // MFMA operand layout (16x16x4 f64, wave64; checked on the device): lane l holds A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator register r of lane l holds D[4 r + l / 16][l % 16].
@@ -942,469 +942,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 }
 
 // ----------------------------------------------------------------------------------------
-// Small dense kernels (m <= 512), column-major complex FP64.
-// ----------------------------------------------------------------------------------------
-__device__ __forceinline__ double2 mkc(double x, double y) { double2 r; r.x = x; r.y = y; return r; }
-__device__ __forceinline__ double2 conjd(double2 a) { return mkc(a.x, -a.y); }
-
-__global__ void k_small_gemm(int tA, int tB, int m, int n, int k, double2 alpha, const double2* __restrict__ A,
-                             int lda, const double2* __restrict__ B, int ldb, double2 beta, double2* C, int ldc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= m || j >= n) return;
-    double sx = 0, sy = 0;
-    for (int l = 0; l < k; ++l) {
-        double2 a = tA ? conjd(A[(long long)i * lda + l]) : A[(long long)l * lda + i];
-        double2 b = tB ? conjd(B[(long long)l * ldb + j]) : B[(long long)j * ldb + l];
-        sx += a.x * b.x - a.y * b.y;
-        sy += a.x * b.y + a.y * b.x;
-    }
-    double2 s = mkc(alpha.x * sx - alpha.y * sy, alpha.x * sy + alpha.y * sx);
-    double2* dst = C + (long long)j * ldc + i;
-    if (beta.x != 0.0 || beta.y != 0.0) {
-        double2 o = *dst;
-        s.x += beta.x * o.x - beta.y * o.y;
-        s.y += beta.x * o.y + beta.y * o.x;
-    }
-    *dst = s;
-}
-
-// Right-looking Cholesky A = L L^H in one workgroup; lower triangle kept, upper zeroed.
-// Workgroup b factors problem b of the launch (two independent matrices of one size).
-__global__ void __launch_bounds__(1024) k_small_cholesky(int m, int lda, double2* A0, int* info0, double2* A1,
-                                                         int* info1) {
-    double2* A = blockIdx.x ? A1 : A0;
-    int* info = blockIdx.x ? info1 : info0;
-    __shared__ double piv;
-    __shared__ int bad;
-    const int t = threadIdx.x, nt = blockDim.x;
-    if (t == 0) bad = 0;
-    __syncthreads();
-    for (int j = 0; j < m; ++j) {
-        if (t == 0) {
-            double d = A[(long long)j * lda + j].x;
-            if (!(d > 0.0) || !isfinite(d)) { bad = j + 1; piv = 1.0; }
-            else piv = sqrt(d);
-        }
-        __syncthreads();
-        if (bad) break;
-        const double inv = 1.0 / piv;
-        for (int i = j + t; i < m; i += nt) {
-            double2 v = A[(long long)j * lda + i];
-            A[(long long)j * lda + i] = (i == j) ? mkc(piv, 0.0) : mkc(v.x * inv, v.y * inv);
-        }
-        __syncthreads();
-        // trailing update: A[i][l] -= L[i][j] conj(L[l][j]) for j < l <= i
-        const int rem = m - j - 1;
-        const long long tot = (long long)rem * rem;
-        for (long long e = t; e < tot; e += nt) {
-            const int i = j + 1 + (int)(e % rem), l = j + 1 + (int)(e / rem);
-            if (l > i) continue;
-            double2 li = A[(long long)j * lda + i], ll = A[(long long)j * lda + l];
-            double2* d = A + (long long)l * lda + i;
-            double2 o = *d;
-            o.x -= li.x * ll.x + li.y * ll.y;
-            o.y -= li.y * ll.x - li.x * ll.y;
-            *d = o;
-        }
-        __syncthreads();
-    }
-    __syncthreads();
-    // zero the strict upper triangle
-    for (long long e = t; e < (long long)m * m; e += nt) {
-        const int i = (int)(e % m), l = (int)(e / m);
-        if (l > i) A[(long long)l * lda + i] = mkc(0.0, 0.0);
-    }
-    if (t == 0) *info = bad;
-}
-
-// One-sided Jacobi SVD by column blocks (round-robin ordering of blocks, complex rotations).
-// A launch processes one round: workgroup b takes a pair of blocks of W columns and runs one
-// sweep over all pairs of its 2W columns (k_bjacobi_round_g).  Rotations of columns whose
-// squared norm is below negl (1e-30 ||G||_F^2) are skipped: such columns are numerically zero.
-__global__ void k_identity_frob(int rows, int m, const double2* __restrict__ G, int ldg, double2* V, int ldv,
-                                double* frob2, int* counter) {
-    __shared__ double red[16];
-    double fs = 0;
-    for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
-        const int i = (int)(e % m), l = (int)(e / m);
-        V[(long long)l * ldv + i] = mkc(i == l ? 1.0 : 0.0, 0.0);
-    }
-    for (long long e = threadIdx.x; e < (long long)rows * m; e += blockDim.x) {
-        const double2 g = G[(e / rows) * ldg + e % rows];
-        fs += g.x * g.x + g.y * g.y;
-    }
-    for (int off = 32; off > 0; off >>= 1) fs += __shfl_down(fs, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fs;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0;
-        for (int w = 0; w < (int)(blockDim.x / 64); ++w) a += red[w];
-        *frob2 = a;
-        *counter = 0;
-    }
-}
-
-__global__ void k_zero_int(int* p) { *p = 0; }
-
-// One round of the block one-sided Jacobi: the workgroup stages its 2W columns of G, forms their
-// Gram matrix A = C^H C, runs the sweep over all pairs of its 2W columns on A alone
-// (A <- R^H A R per disjoint pair, two LDS phases per step) while accumulating the unitary
-// J = prod R, and applies J once to the 2W columns of G and V.  The rotations are those of
-// the column form (they are computed from the same inner products); the per-step work is two
-// LDS entries per thread instead of a pass over all rows.
-template <int W>
-__global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double2* G, int ldg, double2* V, int ldv,
-                                                         int nblk, int rnd, const double* __restrict__ frob2,
-                                                         int* rotations, double conv) {
-    constexpr int N2 = 2 * W, PA = N2 + 1;
-    extern __shared__ double2 sm[];
-    __shared__ double prm[W][4];
-    __shared__ int pact[W];
-    __shared__ int rot_any;
-    const int t = threadIdx.x, nt = blockDim.x;
-    auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (nblk - 1)) + 1; };
-    const int P = player(blockIdx.x), Q = player(nblk - 1 - blockIdx.x);
-    const int c0[2] = {P * W, Q * W};
-    int nc[2];
-    for (int h = 0; h < 2; ++h) {
-        const int lim = m - c0[h];
-        nc[h] = lim <= 0 ? 0 : (lim < W ? lim : W);
-    }
-    auto valid = [&](int k) { return (k % W) < nc[k / W]; };
-    auto colidx = [&](int k) { return c0[k / W] + (k % W); };
-    const int pg = rows | 1;
-    double2* lg = sm;                          // N2 columns of G, pitch pg
-    double2* A = lg + (size_t)N2 * pg;         // N2 x N2, pitch PA
-    double2* J = A + N2 * PA;                  // N2 x N2, pitch PA
-    if (t == 0) rot_any = 0;
-    {
-        // 256 / N2 threads per column, 8 loads in flight per thread (the round is latency-bound)
-        constexpr int TPC = 256 / N2, U = 8;
-        const int kc = t / TPC, lane = t % TPC;
-        const bool vk = valid(kc);
-        const double2* src = G + (long long)(vk ? colidx(kc) : 0) * ldg;
-        for (int i0 = lane; i0 < rows; i0 += U * TPC) {
-            double2 v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * TPC;
-                v[u] = (vk && i < rows) ? src[i] : mkc(0.0, 0.0);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * TPC;
-                if (i < rows) lg[kc * pg + i] = v[u];
-            }
-        }
-    }
-    __syncthreads();
-    for (int e = t; e < N2 * N2; e += nt) {
-        const int r = e % N2, c = e / N2;
-        if (r <= c) {
-            double sx = 0, sy = 0;
-            for (int i = 0; i < rows; ++i) {
-                const double2 a = lg[r * pg + i], b = lg[c * pg + i];
-                sx += a.x * b.x + a.y * b.y;
-                sy += a.x * b.y - a.y * b.x;
-            }
-            A[c * PA + r] = mkc(sx, sy);            // conj(c_r) . c_c
-            if (r != c) A[r * PA + c] = mkc(sx, -sy);
-        }
-        J[c * PA + r] = mkc(r == c ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    const double negl = 1e-30 * (*frob2);
-    const double tol = 1e-15;
-    const int tpp = nt / W;
-    const int pair = t / tpp, sub = t % tpp;
-    for (int r2 = 0; r2 < N2 - 1; ++r2) {
-        auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (N2 - 1)) + 1; };
-        int p = pl(pair), q = pl(N2 - 1 - pair);
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
-        if (sub == 0 && pair < W) {
-            int act = 0;
-            if (valid(p) && valid(q)) {
-                const double al = A[p * PA + p].x, be = A[q * PA + q].x;
-                const double2 gm = A[q * PA + p];
-                const double g = sqrt(gm.x * gm.x + gm.y * gm.y);
-                if (g > tol * sqrt(al * be) && g > 0.0 && al > negl && be > negl) {
-                    if (g > conv * sqrt(al * be)) rot_any = 1;
-                    const double zeta = (be - al) / (2.0 * g);
-                    const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
-                                                         : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt);
-                    prm[pair][0] = cs;
-                    prm[pair][1] = cs * tt;
-                    prm[pair][2] = gm.x / g;     // e = conj(gamma) / |gamma|
-                    prm[pair][3] = -gm.y / g;
-                    act = 1;
-                }
-            }
-            pact[pair] = act;
-        }
-        __syncthreads();
-        const bool act = pair < W && pact[pair];
-        double cs = 0, sn = 0, ex = 0, ey = 0;
-        if (act) { cs = prm[pair][0]; sn = prm[pair][1]; ex = prm[pair][2]; ey = prm[pair][3]; }
-        if (act) {
-            // columns p, q of A and J: [a, b] <- [cs a - sn e b, sn a + cs e b]
-            for (int i = sub; i < N2; i += tpp) {
-                double2 a = A[p * PA + i], b = A[q * PA + i];
-                double2 eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
-                A[p * PA + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                A[q * PA + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
-                a = J[p * PA + i];
-                b = J[q * PA + i];
-                eb = mkc(ex * b.x - ey * b.y, ex * b.y + ey * b.x);
-                J[p * PA + i] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                J[q * PA + i] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
-            }
-        }
-        __syncthreads();
-        if (act) {
-            // rows p, q of A: [a; b] <- [cs a - sn conj(e) b; sn a + cs conj(e) b]
-            for (int j = sub; j < N2; j += tpp) {
-                const double2 a = A[j * PA + p], b = A[j * PA + q];
-                const double2 eb = mkc(ex * b.x + ey * b.y, ex * b.y - ey * b.x);
-                A[j * PA + p] = mkc(cs * a.x - sn * eb.x, cs * a.y - sn * eb.y);
-                A[j * PA + q] = mkc(sn * a.x + cs * eb.x, sn * a.y + cs * eb.y);
-            }
-        }
-        __syncthreads();
-    }
-    // [G; V] columns <- [G; V] columns J (row-local: each thread owns whole rows)
-    for (int i = t; i < rows + m; i += nt) {
-        const bool isg = i < rows;
-        const int ii = isg ? i : i - rows;
-        double2 x[N2];
-#pragma unroll
-        for (int k = 0; k < N2; ++k)
-            x[k] = isg ? lg[k * pg + ii] : (valid(k) ? V[(long long)colidx(k) * ldv + ii] : mkc(0.0, 0.0));
-#pragma unroll
-        for (int c = 0; c < N2; ++c) {
-            if (!valid(c)) continue;
-            double sx = 0, sy = 0;
-#pragma unroll
-            for (int k = 0; k < N2; ++k) {
-                const double2 jj = J[c * PA + k];
-                sx += x[k].x * jj.x - x[k].y * jj.y;
-                sy += x[k].x * jj.y + x[k].y * jj.x;
-            }
-            if (isg) G[(long long)colidx(c) * ldg + ii] = mkc(sx, sy);
-            else V[(long long)colidx(c) * ldv + ii] = mkc(sx, sy);
-        }
-    }
-    if (t == 0 && rot_any) atomicAdd(rotations, 1);
-}
-
-// The same round for real matrices held in complex storage (imaginary parts zero, as in the
-// paired real form): real rotations (the phase e reduces to the sign of the off-diagonal
-// entry), staging of the real parts only (half the LDS), a quarter of the flops.  Staging
-// and the V rows keep several loads in flight per thread: the round is latency-bound.
-template <int W>
-__global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double2* G, int ldg, double2* V, int ldv,
-                                                         int nblk, int rnd, const double* __restrict__ frob2,
-                                                         int* rotations, double conv) {
-    constexpr int N2 = 2 * W, PA = N2 + 1, TPC = 256 / N2, U = 8;
-    static_assert(256 % N2 == 0, "columns divide the workgroup");
-    extern __shared__ double smr[];
-    __shared__ int rot_any;
-    const int t = threadIdx.x;
-    auto player = [&](int s) { return s == 0 ? 0 : ((s - 1 + rnd) % (nblk - 1)) + 1; };
-    const int P = player(blockIdx.x), Q = player(nblk - 1 - blockIdx.x);
-    const int c0[2] = {P * W, Q * W};
-    int nc[2];
-    for (int h = 0; h < 2; ++h) {
-        const int lim = m - c0[h];
-        nc[h] = lim <= 0 ? 0 : (lim < W ? lim : W);
-    }
-    auto valid = [&](int k) { return (k % W) < nc[k / W]; };
-    auto colidx = [&](int k) { return c0[k / W] + (k % W); };
-    const int pg = rows | 1;
-    double* lg = smr;                          // N2 columns of G, pitch pg
-    double* A = lg + (size_t)N2 * pg;          // N2 x N2, pitch PA
-    double* J = A + N2 * PA;                   // N2 x N2, pitch PA
-    if (t == 0) rot_any = 0;
-    {
-        // TPC threads per column, U loads in flight per thread
-        const int kc = t / TPC, lane = t % TPC;
-        const bool vk = valid(kc);
-        const double2* src = G + (long long)(vk ? colidx(kc) : 0) * ldg;
-        for (int i0 = lane; i0 < rows; i0 += U * TPC) {
-            double v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * TPC;
-                v[u] = (vk && i < rows) ? src[i].x : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * TPC;
-                if (i < rows) lg[kc * pg + i] = v[u];
-            }
-        }
-    }
-    __syncthreads();
-    for (int e = t; e < N2 * N2; e += 256) {
-        const int r = e % N2, c = e / N2;
-        if (r <= c) {
-            const double* a = lg + r * pg;
-            const double* b = lg + c * pg;
-            double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            int i = 0;
-            for (; i + 4 <= rows; i += 4) {
-                s0 += a[i] * b[i];
-                s1 += a[i + 1] * b[i + 1];
-                s2 += a[i + 2] * b[i + 2];
-                s3 += a[i + 3] * b[i + 3];
-            }
-            for (; i < rows; ++i) s0 += a[i] * b[i];
-            const double sx = (s0 + s1) + (s2 + s3);
-            A[c * PA + r] = sx;
-            A[r * PA + c] = sx;
-        }
-        J[c * PA + r] = r == c ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    const double negl = 1e-30 * (*frob2);
-    const double tol = 1e-15;
-    constexpr int tpp = 256 / W;
-    const int pair = t / tpp, sub = t % tpp;
-    for (int r2 = 0; r2 < N2 - 1; ++r2) {
-        auto pl = [&](int s) { return s == 0 ? 0 : ((s - 1 + r2) % (N2 - 1)) + 1; };
-        int p = pl(pair), q = pl(N2 - 1 - pair);
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
-        // every thread of the pair computes the rotation itself (same inputs, same result), so
-        // no barrier separates the parameters from the updates
-        bool act = false;
-        double cs = 0, sn = 0, ex = 0;
-        if (valid(p) && valid(q)) {
-            const double al = A[p * PA + p], be = A[q * PA + q];
-            const double gm = A[q * PA + p];
-            const double g = fabs(gm);
-            const double sab = sqrt(al * be);
-            if (g > tol * sab && g > 0.0 && al > negl && be > negl) {
-                if (g > conv * sab && sub == 0) rot_any = 1;
-                const double zeta = (be - al) / (2.0 * g);
-                const double tt = fabs(zeta) > 1e100 ? 0.5 / zeta
-                                                     : (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                cs = 1.0 / sqrt(1.0 + tt * tt);
-                sn = cs * tt;
-                ex = gm >= 0.0 ? 1.0 : -1.0;    // e = sign(gamma)
-                act = true;
-            }
-        }
-        if (act) {
-            // columns p, q of A and J: [a, b] <- [cs a - sn e b, sn a + cs e b]
-            for (int i = sub; i < N2; i += tpp) {
-                double a = A[p * PA + i], b = ex * A[q * PA + i];
-                A[p * PA + i] = cs * a - sn * b;
-                A[q * PA + i] = sn * a + cs * b;
-                a = J[p * PA + i];
-                b = ex * J[q * PA + i];
-                J[p * PA + i] = cs * a - sn * b;
-                J[q * PA + i] = sn * a + cs * b;
-            }
-        }
-        __syncthreads();
-        if (act) {
-            // rows p, q of A
-            for (int j = sub; j < N2; j += tpp) {
-                const double a = A[j * PA + p], b = ex * A[j * PA + q];
-                A[j * PA + p] = cs * a - sn * b;
-                A[j * PA + q] = sn * a + cs * b;
-            }
-        }
-        __syncthreads();
-    }
-    // [G; V] columns <- [G; V] columns J on the FP64 matrix cores: the rows + m rows in blocks
-    // of 16 (G rows from LDS, V rows from memory), D = X J over N2 / 4 steps of four columns
-    // of X; register r of lane l holds D[4 r + l / 16][l % 16], a lane's A operand is
-    // X[l % 16][l / 16] and its B operand J[l / 16][l % 16] of the step
-    {
-        const int wave = t >> 6, lane = t & 63;
-        const int li = lane & 15, lk = lane >> 4;
-        const int nrb = (rows + m + 15) / 16;
-        for (int rb = wave; rb < nrb; rb += 4) {
-            const int row = 16 * rb + li;                  // this lane's A row
-            const bool rg = row < rows;
-            const bool rv = !rg && row < rows + m;
-            d4 acc[N2 / 16 > 0 ? N2 / 16 : 1];
-#pragma unroll
-            for (int cb = 0; cb < (N2 + 15) / 16; ++cb) acc[cb] = d4{0, 0, 0, 0};
-#pragma unroll
-            for (int kc = 0; kc < N2 / 4; ++kc) {
-                const int kk = 4 * kc + lk;
-                const double a = rg ? lg[kk * pg + row]
-                                    : ((rv && valid(kk)) ? V[(long long)colidx(kk) * ldv + (row - rows)].x : 0.0);
-#pragma unroll
-                for (int cb = 0; cb < (N2 + 15) / 16; ++cb) {
-                    const int cc = 16 * cb + li;
-                    const double b = cc < N2 ? J[cc * PA + kk] : 0.0;
-                    acc[cb] = mfma(a, b, acc[cb]);
-                }
-            }
-#pragma unroll
-            for (int cb = 0; cb < (N2 + 15) / 16; ++cb) {
-                const int cc = 16 * cb + li;
-                if (cc >= N2 || !valid(cc)) continue;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int orow = 16 * rb + 4 * r + lk;
-                    if (orow < rows) G[(long long)colidx(cc) * ldg + orow] = mkc(acc[cb][r], 0.0);
-                    else if (orow < rows + m) V[(long long)colidx(cc) * ldv + (orow - rows)] = mkc(acc[cb][r], 0.0);
-                }
-            }
-        }
-    }
-    if (t == 0 && rot_any) atomicAdd(rotations, 1);
-}
-
-// column norms of G (rows x m) into s; permutation to descending order (stable), applied to
-// G and V through the copies Gs, Vs.
-__global__ void __launch_bounds__(1024) k_small_sort(int rows, int m, double2* G, int ldg, double2* V, int ldv,
-                                                    double* s, double2* Gs, double2* Vs) {
-    __shared__ double nrm[512];
-    __shared__ int perm[512];
-    const int t = threadIdx.x;
-    for (int j = t; j < m; j += blockDim.x) {
-        double a = 0;
-        for (int i = 0; i < rows; ++i) {
-            double2 v = G[(long long)j * ldg + i];
-            a += v.x * v.x + v.y * v.y;
-        }
-        nrm[j] = sqrt(a);
-    }
-    __syncthreads();
-    for (int j = t; j < m; j += blockDim.x) {
-        int rank = 0;
-        for (int i = 0; i < m; ++i)
-            if (nrm[i] > nrm[j] || (nrm[i] == nrm[j] && i < j)) ++rank;
-        perm[rank] = j;
-    }
-    __syncthreads();
-    for (long long e = t; e < (long long)rows * m; e += blockDim.x) {
-        const int i = (int)(e % rows), l = (int)(e / rows);
-        Gs[e] = G[(long long)l * ldg + i];
-    }
-    for (long long e = t; e < (long long)m * m; e += blockDim.x) {
-        const int i = (int)(e % m), l = (int)(e / m);
-        Vs[e] = V[(long long)l * ldv + i];
-    }
-    __syncthreads();
-    for (long long e = t; e < (long long)rows * m; e += blockDim.x) {
-        const int i = (int)(e % rows), l = (int)(e / rows);
-        G[(long long)l * ldg + i] = Gs[(long long)perm[l] * rows + i];
-    }
-    for (long long e = t; e < (long long)m * m; e += blockDim.x) {
-        const int i = (int)(e % m), l = (int)(e / m);
-        V[(long long)l * ldv + i] = Vs[(long long)perm[l] * m + i];
-    }
-    for (int j = t; j < m; j += blockDim.x) s[j] = nrm[perm[j]];
-}
-
-// ----------------------------------------------------------------------------------------
 // Column reductions (two-stage, fixed order)
 // ----------------------------------------------------------------------------------------
 constexpr int RB = 256;
@@ -1877,97 +1414,6 @@ bdg_status dot_pair(bdg_ctx* c, long long K, int ncols, const double2* F, const 
     hipLaunchKernelGGL(k_colnorm2_final, dim3((unsigned)((2 * ncols + 127) / 128)), dim3(128), 0, c->stream,
                        2 * ncols, nchunk, (const double*)ws, out_dev);
     return hip_check(c, hipGetLastError(), "k_dot_pair");
-}
-
-bdg_status small_gemm(bdg_ctx* c, int transA, int transB, int m, int n, int k, double2 alpha, const double2* A,
-                      int lda, const double2* B, int ldb, double2 beta, double2* C, int ldc) {
-    if (m <= 0 || n <= 0) return BDG_OK;
-    dim3 grid((unsigned)((m + 127) / 128), (unsigned)n);
-    hipLaunchKernelGGL(k_small_gemm, grid, dim3(128), 0, c->stream, transA, transB, m, n, k, alpha, A, lda, B, ldb,
-                       beta, C, ldc);
-    return hip_check(c, hipGetLastError(), "k_small_gemm");
-}
-
-bdg_status small_cholesky(bdg_ctx* c, int m, double2* A, int lda, int* info_dev) {
-    if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_cholesky: m > 512");
-    hipLaunchKernelGGL(k_small_cholesky, dim3(1), dim3(1024), 0, c->stream, m, lda, A, info_dev, A, info_dev);
-    return hip_check(c, hipGetLastError(), "k_small_cholesky");
-}
-
-bdg_status small_cholesky2(bdg_ctx* c, int m, double2* A0, double2* A1, int lda, int* info0_dev, int* info1_dev) {
-    if (m > 512) return ctx_fail(c, BDG_EINVAL, "small_cholesky: m > 512");
-    hipLaunchKernelGGL(k_small_cholesky, dim3(2), dim3(1024), 0, c->stream, m, lda, A0, info0_dev, A1, info1_dev);
-    return hip_check(c, hipGetLastError(), "k_small_cholesky");
-}
-
-bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* V, int ldv, double* s, double conv,
-                     bool real) {
-    if (m <= 0) return BDG_OK;
-    if (m > 512 || rows > 512) return ctx_fail(c, BDG_EINVAL, "small_svd: size out of range");
-    static int lds_limit = 0;
-    if (lds_limit == 0) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || v <= 0)
-            v = 64 * 1024;
-        lds_limit = v;
-    }
-    // block width W: the 2W staged columns of G and the two 2W x 2W matrices (Gram and the
-    // accumulated rotation) must fit in the workgroup's LDS
-    const size_t esz = real ? sizeof(double) : sizeof(double2);
-    auto lds_need = [&](int w) {
-        return ((size_t)2 * w * (size_t)(rows | 1) + (size_t)2 * (2 * w) * (2 * w + 1)) * esz + 1024;
-    };
-    // W = 8 measured fastest on the 2-D and 3-D solves and on 80..240-column real matrices
-    // (a round's time grows with W^2, the number of rounds falls with W); 16 and 4 are kept
-    // for the LDS fallback
-    int w = 8;
-    while (w > 4 && lds_need(w) > (size_t)lds_limit) w >>= 1;
-    if (lds_need(w) > (size_t)lds_limit)
-        return ctx_fail(c, BDG_EINVAL, "small_svd: matrix too large for the LDS-staged Jacobi");
-    int nblk = (m + w - 1) / w;
-    if (nblk < 2) nblk = 2;
-    if (nblk & 1) ++nblk;
-    void* aux = nullptr;
-    BDG_TRY(ctx_scratch(c, 3, 64, &aux));
-    double* frob2 = (double*)aux;
-    int* counter = (int*)((char*)aux + 16);
-    hipLaunchKernelGGL(k_identity_frob, dim3(1), dim3(1024), 0, c->stream, rows, m, (const double2*)G, ldg, V, ldv,
-                       frob2, counter);
-    BDG_HIP(c, hipGetLastError());
-    const size_t lds = lds_need(w) - 1024;
-    const void* kern = real ? (w == 16 ? (const void*)k_bjacobi_round_r<16>
-                               : w == 8 ? (const void*)k_bjacobi_round_r<8> : (const void*)k_bjacobi_round_r<4>)
-                            : (w == 16 ? (const void*)k_bjacobi_round_g<16>
-                               : w == 8 ? (const void*)k_bjacobi_round_g<8> : (const void*)k_bjacobi_round_g<4>);
-    BDG_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-#define BDG_ROUND(KN, WV)                                                                                         \
-    hipLaunchKernelGGL(KN<WV>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V, ldv, nblk, rnd,   \
-                       (const double*)frob2, counter, conv)
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, counter);
-        for (int rnd = 0; rnd < nblk - 1; ++rnd) {
-            if (real) {
-                if (w == 16) BDG_ROUND(k_bjacobi_round_r, 16);
-                else if (w == 8) BDG_ROUND(k_bjacobi_round_r, 8);
-                else BDG_ROUND(k_bjacobi_round_r, 4);
-            } else {
-                if (w == 16) BDG_ROUND(k_bjacobi_round_g, 16);
-                else if (w == 8) BDG_ROUND(k_bjacobi_round_g, 8);
-                else BDG_ROUND(k_bjacobi_round_g, 4);
-            }
-        }
-        BDG_HIP(c, hipGetLastError());
-        int h = 0;
-        BDG_HIP(c, hipMemcpyAsync(&h, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        BDG_HIP(c, hipStreamSynchronize(c->stream));
-        if (h == 0) break;
-    }
-#undef BDG_ROUND
-    void* ws = nullptr;
-    BDG_TRY(ctx_scratch(c, 1, ((size_t)rows * m + (size_t)m * m) * sizeof(double2), &ws));
-    hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, c->stream, rows, m, G, ldg, V, ldv, s, (double2*)ws,
-                       (double2*)ws + (size_t)rows * m);
-    return hip_check(c, hipGetLastError(), "k_small_sort");
 }
 
 bdg_status colnorm2(bdg_ctx* c, long long K, int ncols, const double2* X, long long ldx, double* out_dev) {
