@@ -44,14 +44,24 @@ __device__ void block_argmax(double v, int idx, double* sv, int* si, double* out
     __syncthreads();
 }
 
+// Trailing updates of the factorizations below run in passes of 256 rows: lane l of wave w
+// owns the rows r0 + l + 64 s (s < TR) of the pass and the wave the columns c0 + w + 16 n,
+// TC columns at a time so that their loads are in flight together.  The values of the pivot
+// column that a lane's rows need are loaded once per pass.
+constexpr int TR = 4, TC = 2;
+// element i of a column whose base is wave-uniform: a scalar base plus a 32-bit row offset
+__device__ __forceinline__ double2* col_at(double2* col, int i) {
+    return reinterpret_cast<double2*>(reinterpret_cast<char*>(col) + (unsigned)i * 16u);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // T (r x r, ld r) = Lt^-1 for the lower-triangular Lt given by the accessor (unit: diagonal 1).
 template <typename Acc>
 __device__ void lower_inverse(int r, Acc L, bool unit, double2* T) {
     const int t = threadIdx.x, nt = blockDim.x;
-    for (long long e = t; e < (long long)r * r; e += nt) {
-        const int i = (int)(e % r), c = (int)(e / r);
-        T[(long long)c * r + i] = mk(i == c ? 1.0 : 0.0, 0.0);
-    }
+    const int wv = uniform(t >> 6), ln = t & 63, nw = nt >> 6;
+    for (int c = wv; c < r; c += nw)
+        for (int i = ln; i < r; i += 64) T[(long long)c * r + i] = mk(i == c ? 1.0 : 0.0, 0.0);
     __syncthreads();
     for (int k = 0; k < r; ++k) {
         if (!unit) {
@@ -59,24 +69,45 @@ __device__ void lower_inverse(int r, Acc L, bool unit, double2* T) {
             for (int c = t; c <= k; c += nt) T[(long long)c * r + k] = cdiv(T[(long long)c * r + k], d);
             __syncthreads();
         }
-        const long long rows = r - k - 1, cols = k + 1, nu = rows * cols;
-        for (long long e0 = t; e0 < nu; e0 += 4 * nt) {
-            double2 yv[4], pv[4];
-            long long ix[4];
+        // rows i > k of the columns c <= k: T[c][i] -= L(i, k) T[c][k]
+        for (int r0 = k + 1; r0 < r; r0 += 64 * TR) {
+            double2 lik[TR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const long long e = e0 + (long long)u * nt;
-                ix[u] = -1;
-                if (e < nu) {
-                    const int i = k + 1 + (int)(e % rows), c = (int)(e / rows);
-                    ix[u] = (long long)c * r + i;
-                    pv[u] = cm(L(i, k), T[(long long)c * r + k]);
-                    yv[u] = T[ix[u]];
+            for (int s = 0; s < TR; ++s) {
+                const int i = r0 + ln + 64 * s;
+                lik[s] = i < r ? L(i, k) : mk(0.0, 0.0);
+            }
+            for (int c0 = wv; c0 <= k; c0 += TC * nw) {
+                double2 tck[TC], yv[TC][TR];
+#pragma unroll
+                for (int u = 0; u < TC; ++u) {
+                    const int c = c0 + u * nw;
+                    if (c <= k) {
+                        double2* col = T + (long long)c * r;
+                        tck[u] = col[k];
+#pragma unroll
+                        for (int s = 0; s < TR; ++s) {
+                            const int i = r0 + ln + 64 * s;
+                            if (i < r) yv[u][s] = *col_at(col, i);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < TC; ++u) {
+                    const int c = c0 + u * nw;
+                    if (c <= k) {
+                        double2* col = T + (long long)c * r;
+#pragma unroll
+                        for (int s = 0; s < TR; ++s) {
+                            const int i = r0 + ln + 64 * s;
+                            if (i < r) {
+                                const double2 pv = cm(lik[s], tck[u]);
+                                *col_at(col, i) = mk(yv[u][s].x - pv.x, yv[u][s].y - pv.y);
+                            }
+                        }
+                    }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ix[u] >= 0) T[ix[u]] = mk(yv[u].x - pv[u].x, yv[u].y - pv[u].y);
         }
         __syncthreads();
     }
@@ -163,26 +194,46 @@ __global__ void __launch_bounds__(1024) k_pchol_orth(int m, int lda, double rtol
         }
         __syncthreads();
         // Schur complement update on the remaining rows/columns, lower triangle (original
-        // index order) only; four updates in flight
-        const long long rem = m - j - 1;
-        for (long long e0 = t; e0 < rem * rem; e0 += 4 * nt) {
-            double2 av[4], pv[4];
-            long long ix[4];
+        // index order) only
+        {
+            const int wv = uniform(t >> 6), ln = t & 63, nw = nt >> 6;
+            double2* lcol = Lb + (long long)j * m;
+            for (int r0 = j + 1; r0 < m; r0 += 64 * TR) {
+                int pir[TR];
+                double2 lr[TR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const long long e = e0 + (long long)u * nt;
-                ix[u] = -1;
-                const int pi = e < rem * rem ? perm[j + 1 + (int)(e % rem)] : 0;
-                const int pl = e < rem * rem ? perm[j + 1 + (int)(e / rem)] : 1;
-                if (e < rem * rem && pi >= pl) {
-                    ix[u] = (long long)pl * lda + pi;
-                    pv[u] = cmc(Lb[(long long)j * m + pi], Lb[(long long)j * m + pl]);
-                    av[u] = A[ix[u]];
+                for (int s = 0; s < TR; ++s) {
+                    const int i = r0 + ln + 64 * s;
+                    pir[s] = i < m ? perm[i] : -1;
+                    lr[s] = i < m ? *col_at(lcol, pir[s]) : mk(0.0, 0.0);
+                }
+                for (int l0 = j + 1 + wv; l0 < m; l0 += TC * nw) {
+                    int pl[TC];
+                    double2 ll[TC], av[TC][TR];
+#pragma unroll
+                    for (int u = 0; u < TC; ++u) {
+                        const int l = l0 + u * nw;
+                        pl[u] = l < m ? uniform(perm[l]) : 0x7fffffff;
+                        if (l < m) {
+                            double2* acol = A + (long long)pl[u] * lda;
+                            ll[u] = lcol[pl[u]];
+#pragma unroll
+                            for (int s = 0; s < TR; ++s)
+                                if (pir[s] >= pl[u]) av[u][s] = *col_at(acol, pir[s]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < TC; ++u) {
+                        double2* acol = A + (long long)(pl[u] < m ? pl[u] : 0) * lda;
+#pragma unroll
+                        for (int s = 0; s < TR; ++s)
+                            if (pir[s] >= pl[u]) {
+                                const double2 pv = cmc(lr[s], ll[u]);
+                                *col_at(acol, pir[s]) = mk(av[u][s].x - pv.x, av[u][s].y - pv.y);
+                            }
+                    }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ix[u] >= 0) A[ix[u]] = mk(av[u].x - pv[u].x, av[u].y - pv[u].y);
         }
         for (int i = j + 1 + t; i < m; i += nt) {
             const double2 li = Lb[(long long)j * m + perm[i]];
@@ -253,33 +304,54 @@ __global__ void __launch_bounds__(1024) k_plu_biorth(int p, int q, double2* B, i
         }
         __syncthreads();
         // Schur update of the trailing block; the largest updated entry is the next pivot
-        const long long nu = (rp - 1) * (rq - 1);
         double v = -1.0;
         int idx = 0x7fffffff;
-        for (long long e0 = t; e0 < nu; e0 += 4 * nt) {
-            double2 bv[4], pv[4];
-            long long ix[4];
-            int code[4];
+        {
+            const int wv = uniform(t >> 6), ln = t & 63, nw = nt >> 6;
+            constexpr int TL = 1;    // one column at a time: the pivot search needs the registers
+            double2* bcj = B + (long long)uniform(pc[j]) * ldb;
+            const int rj = uniform(pr[j]);
+            for (int r0 = j + 1; r0 < p; r0 += 64 * TR) {
+                int rowi[TR];
+                double2 lv[TR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const long long e = e0 + (long long)u * nt;
-                ix[u] = -1;
-                if (e < nu) {
-                    const int i = j + 1 + (int)(e % (rp - 1)), l = j + 1 + (int)(e / (rp - 1));
-                    ix[u] = (long long)pc[l] * ldb + pr[i];
-                    code[u] = i * 512 + l;
-                    pv[u] = cm(B[(long long)pc[j] * ldb + pr[i]], B[(long long)pc[l] * ldb + pr[j]]);
-                    bv[u] = B[ix[u]];
+                for (int s = 0; s < TR; ++s) {
+                    const int i = r0 + ln + 64 * s;
+                    rowi[s] = i < p ? pr[i] : -1;
+                    lv[s] = i < p ? *col_at(bcj, rowi[s]) : mk(0.0, 0.0);
+                }
+                for (int l0 = j + 1 + wv; l0 < q; l0 += TL * nw) {
+                    double2* bcl[TL];
+                    double2 uv[TL], bv[TL][TR];
+#pragma unroll
+                    for (int u = 0; u < TL; ++u) {
+                        const int l = l0 + u * nw;
+                        bcl[u] = B + (long long)(l < q ? uniform(pc[l]) : 0) * ldb;
+                        if (l < q) {
+                            uv[u] = bcl[u][rj];
+#pragma unroll
+                            for (int s = 0; s < TR; ++s)
+                                if (rowi[s] >= 0) bv[u][s] = *col_at(bcl[u], rowi[s]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < TL; ++u) {
+                        const int l = l0 + u * nw;
+                        if (l < q) {
+#pragma unroll
+                            for (int s = 0; s < TR; ++s)
+                                if (rowi[s] >= 0) {
+                                    const double2 pv = cm(lv[s], uv[u]);
+                                    const double2 nb = mk(bv[u][s].x - pv.x, bv[u][s].y - pv.y);
+                                    *col_at(bcl[u], rowi[s]) = nb;
+                                    const double a = nb.x * nb.x + nb.y * nb.y;
+                                    const int code = (r0 + ln + 64 * s) * 512 + l;
+                                    if (a > v || (a == v && code < idx)) { v = a; idx = code; }
+                                }
+                        }
+                    }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ix[u] >= 0) {
-                    const double2 nb = mk(bv[u].x - pv[u].x, bv[u].y - pv[u].y);
-                    B[ix[u]] = nb;
-                    const double a = nb.x * nb.x + nb.y * nb.y;
-                    if (a > v || (a == v && code[u] < idx)) { v = a; idx = code[u]; }
-                }
         }
         // (block_argmax synchronizes the workgroup before and after)
         block_argmax(v, idx, sv, si, &bestv, &besti);
@@ -377,26 +449,52 @@ __global__ void __launch_bounds__(1024) k_small_cholesky(int m, int lda, double2
         }
         __syncthreads();
         // trailing update: A[i][l] -= L[i][j] conj(L[l][j]) for j < l <= i
-        const int rem = m - j - 1;
-        const long long tot = (long long)rem * rem;
-        for (long long e = t; e < tot; e += nt) {
-            const int i = j + 1 + (int)(e % rem), l = j + 1 + (int)(e / rem);
-            if (l > i) continue;
-            double2 li = A[(long long)j * lda + i], ll = A[(long long)j * lda + l];
-            double2* d = A + (long long)l * lda + i;
-            double2 o = *d;
-            o.x -= li.x * ll.x + li.y * ll.y;
-            o.y -= li.y * ll.x - li.x * ll.y;
-            *d = o;
+        {
+            const int wv = uniform(t >> 6), ln = t & 63, nw = nt >> 6;
+            double2* ajc = A + (long long)j * lda;
+            for (int r0 = j + 1; r0 < m; r0 += 64 * TR) {
+                double2 li[TR];
+#pragma unroll
+                for (int s = 0; s < TR; ++s) {
+                    const int i = r0 + ln + 64 * s;
+                    li[s] = i < m ? *col_at(ajc, i) : mkc(0.0, 0.0);
+                }
+                for (int l0 = j + 1 + wv; l0 < m; l0 += TC * nw) {
+                    double2 ll[TC], o[TC][TR];
+#pragma unroll
+                    for (int u = 0; u < TC; ++u) {
+                        const int l = l0 + u * nw;
+                        if (l < m) {
+                            ll[u] = ajc[l];
+#pragma unroll
+                            for (int s = 0; s < TR; ++s) {
+                                const int i = r0 + ln + 64 * s;
+                                if (i < m && l <= i) o[u][s] = *col_at(A + (long long)l * lda, i);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < TC; ++u) {
+                        const int l = l0 + u * nw;
+#pragma unroll
+                        for (int s = 0; s < TR; ++s) {
+                            const int i = r0 + ln + 64 * s;
+                            if (l < m && i < m && l <= i) {
+                                o[u][s].x -= li[s].x * ll[u].x + li[s].y * ll[u].y;
+                                o[u][s].y -= li[s].y * ll[u].x - li[s].x * ll[u].y;
+                                *col_at(A + (long long)l * lda, i) = o[u][s];
+                            }
+                        }
+                    }
+                }
+            }
         }
         __syncthreads();
     }
     __syncthreads();
     // zero the strict upper triangle
-    for (long long e = t; e < (long long)m * m; e += nt) {
-        const int i = (int)(e % m), l = (int)(e / m);
-        if (l > i) A[(long long)l * lda + i] = mkc(0.0, 0.0);
-    }
+    for (int l = t >> 6; l < m; l += nt >> 6)
+        for (int i = t & 63; i < l; i += 64) A[(long long)l * lda + i] = mkc(0.0, 0.0);
     if (t == 0) *info = bad;
 }
 
