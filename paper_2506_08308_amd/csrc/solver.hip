@@ -104,15 +104,6 @@ __global__ void k_cols_scale(long long K, int ncols, double2* __restrict__ X, lo
     }
 }
 
-__global__ void k_to32(long long K, int ncols, const double2* __restrict__ X, long long ldx, float2* __restrict__ Y,
-                       long long ldy) {
-    const int j = blockIdx.y;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
-        double2 a = X[j * ldx + i];
-        Y[j * ldy + i] = cmk<float2>((float)a.x, (float)a.y);
-    }
-}
-
 __global__ void k_to64(long long K, int ncols, const float2* __restrict__ X, long long ldx, double2* __restrict__ Y,
                        long long ldy) {
     const int j = blockIdx.y;
@@ -269,6 +260,19 @@ __global__ void k_pair_unit_cols(long long K, double2* __restrict__ X, long long
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
         const double2 v = X[T * ld + i];
         X[T * ld + i] = cmk<double2>(c0 * v.x, c1 * v.y);
+    }
+}
+
+// k_pair_unit_cols followed by the float32 copy in one pass: X scaled in place, Y = float(X)
+__global__ void k_pair_unit_to32(long long K, double2* __restrict__ X, long long ld, const double* __restrict__ sq,
+                                 float2* __restrict__ Y, long long ldy) {
+    const int T = blockIdx.y;
+    const double c0 = unit_scale(sq[2 * T]), c1 = unit_scale(sq[2 * T + 1]);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
+        const double2 v = X[T * ld + i];
+        const double2 u = cmk<double2>(c0 * v.x, c1 * v.y);
+        X[T * ld + i] = u;
+        Y[T * ldy + i] = cmk<float2>((float)u.x, (float)u.y);
     }
 }
 
@@ -1206,13 +1210,17 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         BDG_TRY(project_out(c, w, nh, D.Qg, D.pg, Wg, nactc));
         // W and P are scaled to unit columns in memory before they are applied: two real
         // vectors share a complex FFT, whose rounding is relative to the larger of the pair
-        // (see k_pair_axmy_idx); the Gram matrices are then those of unit columns
+        // (see k_pair_axmy_idx); the Gram matrices are then those of unit columns.  With
+        // float32 images the scaling rides in the float32 copy made for the apply
+        const bool w32img = mixed && !force64;
         BDG_TRY(colnorm2_pair(c, nh, nactc, Wf, nh, d_sf + nb));
         BDG_TRY(colnorm2_pair(c, nh, nactc, Wg, nh, d_sg + nb));
-        hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, Wf, nh,
-                           (const double*)(d_sf + nb));
-        hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, Wg, nh,
-                           (const double*)(d_sg + nb));
+        if (!w32img) {
+            hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, Wf, nh,
+                               (const double*)(d_sf + nb));
+            hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, Wg, nh,
+                               (const double*)(d_sg + nb));
+        }
         // P of the active columns only: gather them (and their images) into the free slot
         if (S.slotP >= 0 && nact < nb) {
             for (int a = 0; a < 4; ++a)
@@ -1226,33 +1234,36 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         if (np) {
             BDG_TRY(colnorm2_pair(c, nh, np / 2, S.col(SF, S.slotP), nh, d_sf + nb + nact));
             BDG_TRY(colnorm2_pair(c, nh, np / 2, S.col(SG, S.slotP), nh, d_sg + nb + nact));
-            hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, np / 2), dim3(256), 0, c->stream, nh,
-                               S.col(SF, S.slotP), nh, (const double*)(d_sf + nb + nact));
-            hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, np / 2), dim3(256), 0, c->stream, nh,
-                               S.col(SG, S.slotP), nh, (const double*)(d_sg + nb + nact));
+            if (!w32img) {
+                hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, np / 2), dim3(256), 0, c->stream, nh,
+                                   S.col(SF, S.slotP), nh, (const double*)(d_sf + nb + nact));
+                hipLaunchKernelGGL(k_pair_unit_cols, grid_cols(nh, np / 2), dim3(256), 0, c->stream, nh,
+                                   S.col(SG, S.slotP), nh, (const double*)(d_sg + nb + nact));
+            }
         }
         BDG_HIP(c, hipGetLastError());
         BDG_TRY(sync_if());
         BDG_TRY(mark(1));
         double2* HWf = S.col(HSF, S.slotW);
         double2* HWg = S.col(HSG, S.slotW);
-        const bool w32img = mixed && !force64;
         if (w32img) {
             // W and P (when present) in one float32 launch: f halves [W_f, P_f], g halves
             // [W_g, P_g]; P's images are recomputed from P as in the float64 form below
             const int nv = S.slotP >= 0 ? 2 * nactc : nactc;
             float2* f32 = w32;
             float2* g32 = w32 + (size_t)nv * nh;
-            const double2* src_f[2] = {Wf, S.slotP >= 0 ? S.col(SF, S.slotP) : nullptr};
-            const double2* src_g[2] = {Wg, S.slotP >= 0 ? S.col(SG, S.slotP) : nullptr};
+            double2* src_f[2] = {Wf, S.slotP >= 0 ? S.col(SF, S.slotP) : nullptr};
+            double2* src_g[2] = {Wg, S.slotP >= 0 ? S.col(SG, S.slotP) : nullptr};
+            const double* sq_f[2] = {d_sf + nb, d_sf + nb + nact};
+            const double* sq_g[2] = {d_sg + nb, d_sg + nb + nact};
             double2* dst_hf[2] = {HWf, S.slotP >= 0 ? S.col(HSF, S.slotP) : nullptr};
             double2* dst_hg[2] = {HWg, S.slotP >= 0 ? S.col(HSG, S.slotP) : nullptr};
             const int nparts = S.slotP >= 0 ? 2 : 1;
             for (int q = 0; q < nparts; ++q) {
-                hipLaunchKernelGGL(k_to32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc, src_f[q], nh,
-                                   f32 + (size_t)q * nactc * nh, nh);
-                hipLaunchKernelGGL(k_to32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc, src_g[q], nh,
-                                   g32 + (size_t)q * nactc * nh, nh);
+                hipLaunchKernelGGL(k_pair_unit_to32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, src_f[q], nh,
+                                   sq_f[q], f32 + (size_t)q * nactc * nh, nh);
+                hipLaunchKernelGGL(k_pair_unit_to32, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, src_g[q], nh,
+                                   sq_g[q], g32 + (size_t)q * nactc * nh, nh);
             }
             BDG_HIP(c, hipGetLastError());
             BlockRef<const float2> X{f32, g32, nh};
