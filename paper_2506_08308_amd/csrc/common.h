@@ -142,6 +142,10 @@ bdg_status launch_precond(bdg_ctx* c, int nfields, int fpv, long long vstride,
 // Mixed form of launch_precond on nvec (f, g) pairs: float32 passes in place on X32 (lo: the
 // f halves, hi: the g halves, vector stride vstride), the last pass writes float64 into Y64.
 bdg_status launch_precond_mixed(bdg_ctx* c, int nvec, BlockRef<float2> X32, BlockRef<double2> Y64);
+// the (f, g) operator in float32 on X, its result widened to float64 into Y64 (Ywork: float32
+// work block of X's shape, overwritten)
+bdg_status launch_apply_fg_to64(bdg_ctx* c, int nvec, BlockRef<const float2> X, BlockRef<float2> Ywork,
+                                BlockRef<double2> Y64);
 // complex ground state, (u, v) vectors in float64: kform = 0 gives Y = H X with
 // H = [[T + A, B], [-conj B, -(T + conj A)]]; kform = 1 gives Y = sigma_3 H X, i.e. the
 // Hermitian positive semidefinite K = [[T + A, B], [conj B, T + conj A]]

@@ -528,10 +528,12 @@ __global__ void __launch_bounds__(1024) k_plane_fwd(FieldAddr<const float2> in, 
 // groups and deals their tasks to its workgroups in order, so the three components of a
 // group (which read the same three input planes and coefficient rows) and the groups of one
 // plane (which read the same coefficient planes) run at about the same time on one XCD and
-// share its L2.
-template <int TRANS>
+// share its L2.  The result goes to yout, which is yio itself (float2) or the float64
+// images (double2: the float32 result widened, in place of a separate conversion pass).
+template <int TRANS, typename VO = float2>
 __global__ void __launch_bounds__(1024) k_plane_inv_couple(FieldAddr<const float2> xin, FieldAddr<float2> yio,
-                                                           long long nvec, int nz, const float2* __restrict__ twx,
+                                                           FieldAddr<VO> yout, long long nvec, int nz,
+                                                           const float2* __restrict__ twx,
                                                            const float2* __restrict__ twy,
                                                            const float* __restrict__ coef) {
     extern __shared__ float2 pl[];
@@ -576,7 +578,7 @@ __global__ void __launch_bounds__(1024) k_plane_inv_couple(FieldAddr<const float
         const Task k = task_of(u);
         const int a = k.a, h = k.h;
         const long long poff = k.z * (long long)(PLN * PLN);
-        float2* io = plane_of(k);
+        VO* io = yout.field(k.vec * 6 + 3 * k.h + k.a) + poff;
         // output half 0 (y_f): H_- acting on g (input half 1); half 1 (y_g): H_+ on f (half 0);
         // the transpose exchanges H_+ and H_-
         const int hin = 1 - h;
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(1024) k_plane_inv_couple(FieldAddr<const float
             float2 y;
             y.x = kk.x + m0 * u0.x + m1 * u1.x + m2 * u2.x;
             y.y = kk.y + m0 * u0.y + m1 * u1.y + m2 * u2.y;
-            io[e] = y;
+            io[e] = cmk<VO>(y.x, y.y);
         }
         lds_barrier();
     }
@@ -719,9 +721,11 @@ bdg_status apply_impl(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y
     return BDG_OK;
 }
 
-// the three-pass (f, g) operator of complex64 128 x 128 x nz grids (see k_plane_fwd)
-template <int TRANS>
-bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAddr<float2> Y, MultSpec ms) {
+// the three-pass (f, g) operator of complex64 128 x 128 x nz grids (see k_plane_fwd); Y is
+// the work block of the first two passes, Yout receives the result (Y itself, or float64)
+template <int TRANS, typename VO = float2>
+bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAddr<float2> Y, FieldAddr<VO> Yout,
+                        MultSpec ms) {
     static bool lds_set = false;
     if (!lds_set) {
         BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -729,6 +733,8 @@ bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAd
         BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple<0>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
         BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple<1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple<0, double2>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
         lds_set = true;
     }
@@ -741,8 +747,8 @@ bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAd
     BDG_TRY(hip_check(c, hipGetLastError(), "k_plane_fwd"));
     BDG_TRY((run_strided<float2, false, 1>(c, Y, nf, 2, ms)));
     const unsigned grid_inv = (unsigned)std::max<long long>(8, std::min<long long>(ntask, c->ncu));
-    hipLaunchKernelGGL(k_plane_inv_couple<TRANS>, dim3(grid_inv), dim3(1024), PLANE_LDS, c->stream, X, Y,
-                       (long long)nvec, nz, (const float2*)c->tw32[0], (const float2*)c->tw32[1],
+    hipLaunchKernelGGL((k_plane_inv_couple<TRANS, VO>), dim3(grid_inv), dim3(1024), PLANE_LDS, c->stream, X, Y,
+                       Yout, (long long)nvec, nz, (const float2*)c->tw32[0], (const float2*)c->tw32[1],
                        (const float*)c->coef32);
     return hip_check(c, hipGetLastError(), "k_plane_inv_couple");
 }
@@ -753,7 +759,7 @@ bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> 
     const long long nf = 6LL * nvec;
     if constexpr (std::is_same<V, float2>::value && FORM == 1) {
         if (c->apply_planes && c->dim == 3 && c->n[0] == PLN && c->n[1] == PLN)
-            return apply_planes<TRANS>(c, nvec, X, Y, ms);
+            return apply_planes<TRANS>(c, nvec, X, Y, Y, ms);
     }
     if (c->dim == 1) return run_couple<V, FORM, TRANS, true>(c, X, Y, nvec, ms);
     BDG_TRY((run_xpass<V, false, 0>(c, X, Y, nf, ms)));
@@ -765,6 +771,16 @@ bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> 
         BDG_TRY((run_strided<V, true, 0>(c, Y, nf, 1, ms)));
     }
     return run_couple<V, FORM, TRANS, false>(c, X, Y, nvec, ms);
+}
+
+// float32 images widened to float64 (one vector, its 6 fields, per gridDim.y)
+__global__ void k_fields_to64(long long npts3, FieldAddr<const float2> y, FieldAddr<double2> out) {
+    const long long vec = blockIdx.y / 2;
+    const int half = blockIdx.y % 2;
+    const float2* src = y.field(vec * 6 + 3 * half);
+    double2* dst = out.field(vec * 6 + 3 * half);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < npts3; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = cmk<double2>(src[i].x, src[i].y);
 }
 
 }  // namespace
@@ -780,6 +796,24 @@ bdg_status launch_apply(bdg_ctx* c, int form, int transpose, int nvec,
         return transpose ? apply_impl<V, 1, 1>(c, nvec, xa, ya) : apply_impl<V, 1, 0>(c, nvec, xa, ya);
     }
     return transpose ? apply_impl<V, 0, 1>(c, nvec, xa, ya) : apply_impl<V, 0, 0>(c, nvec, xa, ya);
+}
+
+bdg_status launch_apply_fg_to64(bdg_ctx* c, int nvec, BlockRef<const float2> X, BlockRef<float2> Ywork,
+                                BlockRef<double2> Y64) {
+    if (nvec <= 0) return BDG_OK;
+    FieldAddr<const float2> xa = fa_block<const float2>(X.lo, X.hi, X.vstride, c->npts);
+    FieldAddr<float2> wa = fa_block<float2>(Ywork.lo, Ywork.hi, Ywork.vstride, c->npts);
+    FieldAddr<double2> ya = fa_block<double2>(Y64.lo, Y64.hi, Y64.vstride, c->npts);
+    if (c->apply_chunk_bytes == 0 && c->apply_planes && c->dim == 3 && c->n[0] == PLN && c->n[1] == PLN)
+        return apply_planes<0, double2>(c, nvec, xa, wa, ya, make_ms(c, 0, 0.0));
+    BDG_TRY((apply_impl<float2, 1, 0>(c, nvec, xa, wa)));
+    const long long npts3 = 3 * c->npts;
+    long long bx = (npts3 + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    FieldAddr<const float2> wc = fa_block<const float2>(Ywork.lo, Ywork.hi, Ywork.vstride, c->npts);
+    hipLaunchKernelGGL(k_fields_to64, dim3((unsigned)bx, (unsigned)(2 * nvec)), dim3(256), 0, c->stream, npts3, wc,
+                       ya);
+    return hip_check(c, hipGetLastError(), "k_fields_to64");
 }
 
 bdg_status launch_apply_complex(bdg_ctx* c, int kform, int nvec, BlockRef<const double2> X, BlockRef<double2> Y) {

@@ -104,15 +104,6 @@ __global__ void k_cols_scale(long long K, int ncols, double2* __restrict__ X, lo
     }
 }
 
-__global__ void k_to64(long long K, int ncols, const float2* __restrict__ X, long long ldx, double2* __restrict__ Y,
-                       long long ldy) {
-    const int j = blockIdx.y;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
-        float2 a = X[j * ldx + i];
-        Y[j * ldy + i] = cmk<double2>((double)a.x, (double)a.y);
-    }
-}
-
 // Y += alpha X (complex alpha), single column
 __global__ void k_axpy(long long K, double2 alpha, const double2* __restrict__ X, double2* __restrict__ Y) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (long long)gridDim.x * blockDim.x) {
@@ -1266,16 +1257,14 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
                                    sq_g[q], g32 + (size_t)q * nactc * nh, nh);
             }
             BDG_HIP(c, hipGetLastError());
-            BlockRef<const float2> X{f32, g32, nh};
-            BlockRef<float2> Y{y32, y32 + (size_t)nv * nh, nh};   // lo: H_- [W_g, P_g], hi: H_+ [W_f, P_f]
-            BDG_TRY(launch_apply<float>(c, BDG_FORM_FG, 0, nv, X, Y));
+            // one float32 apply per part, its images written in float64 by the last pass
+            // (lo: H_- g, hi: H_+ f; the float32 work block is y32)
             for (int q = 0; q < nparts; ++q) {
-                hipLaunchKernelGGL(k_to64, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc,
-                                   (const float2*)(y32 + (size_t)q * nactc * nh), nh, dst_hg[q], nh);
-                hipLaunchKernelGGL(k_to64, grid_cols(nh, nactc), dim3(256), 0, c->stream, nh, nactc,
-                                   (const float2*)(y32 + (size_t)(nv + q * nactc) * nh), nh, dst_hf[q], nh);
+                BlockRef<const float2> X{f32 + (size_t)q * nactc * nh, g32 + (size_t)q * nactc * nh, nh};
+                BlockRef<float2> Yw{y32 + (size_t)q * nactc * nh, y32 + (size_t)(nv + q * nactc) * nh, nh};
+                BlockRef<double2> Y64{dst_hg[q], dst_hf[q], nh};
+                BDG_TRY(launch_apply_fg_to64(c, nactc, X, Yw, Y64));
             }
-            BDG_HIP(c, hipGetLastError());
             napply32 += 2 * nv;
         } else {
             BDG_TRY(apply64(c, nactc, Wf, Wg, nh, HWf, HWg));
