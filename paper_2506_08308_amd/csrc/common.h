@@ -80,7 +80,8 @@ struct bdg_ctx {
     bool apply_planes = true;
     // symmetric paired Grams of 65..128 complex columns by one workgroup per K-split
     bool gram_wide = true;
-    bool gram_w8 = true;          // ... in blocks of 8 complex columns
+    int gram_w8 = 2;              // ... in blocks of 8 complex columns (2: operands loaded straight to
+                                  // LDS, 1: staged through registers, 0: off)
     // scratch owned by the context (grown on demand)
     DevBuf scratch[8];
     // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out

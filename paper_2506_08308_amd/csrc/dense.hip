@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace {
 
@@ -515,6 +516,147 @@ __global__ void __launch_bounds__(1024) k_gram_pair_w8(long long K, int m1, int 
         for (int r = 0; r < 4; ++r) {
             const int p = 16 * bi[j] + 4 * r + (lane >> 4);
             const int q = 16 * bj[j] + (lane & 15);
+            if (p < 2 * m1 && q < 2 * m2) out[(long long)q * ldr + p] = acc[j][r];
+        }
+    }
+}
+
+// The same Gram with the operands loaded straight into LDS (global_load_lds_dwordx4: lane l
+// of a wave's load writes 16 bytes at the instruction's LDS base + 16 l).  A load fills one
+// block of 8 complex columns x 8 complex rows, lane l taking column l % 8 and row l / 8, so
+// a block holds row r of its columns at slots 8 r .. 8 r + 7.  An MFMA step reads, for lane l,
+// real row l / 16 (complex row kq, part l % 2) of column (l % 16) / 2: in a block that is
+// double 16 kq + l % 16, so a wave reads 512 contiguous bytes.  Chunks of 16 complex rows
+// alternate between two buffers: one barrier per chunk, the loads of the next chunk in
+// flight while this one is multiplied, and no staging registers.  Rows past the end of the
+// split are loaded from its last row and zeroed by the lane that loaded them.
+constexpr int W8B = 16;                      // column blocks per operand (128 complex columns)
+constexpr int W8BUF = 2 * W8B * 128;         // doubles per operand and buffer (32 KiB)
+__global__ void __launch_bounds__(1024) k_gram_pair_w8d(long long K, int m1, int m2, int herm, SegList A,
+                                                       long long lda, SegList B, long long ldb, long long kper,
+                                                       int same, double* __restrict__ part) {
+    // [operand][buffer][column block][row half][64 complex]
+    __shared__ __align__(16) double lds[2 * 2 * W8BUF];
+    const long long split = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const long long ldr = 2LL * m1;
+    double* out = part + split * ldr * (2LL * m2);
+    const long long k0 = split * kper;
+    long long k1 = k0 + kper;
+    if (k1 > K) k1 = K;
+    const int nb1 = (m1 + 7) / 8, nb2 = (m2 + 7) / 8;
+    const int ntile = herm ? nb1 * (nb1 + 1) / 2 : nb1 * nb2;
+    const int base = ntile / 16, extra = ntile % 16;
+    const int first = wave * base + (wave < extra ? wave : extra);
+    const int cnt = base + (wave < extra ? 1 : 0);
+    // this lane's read addresses (bytes) of each tile's A and B blocks, row half 0, buffer 0
+    unsigned ra[W8T], rb[W8T];
+#pragma unroll
+    for (int j = 0; j < W8T; ++j) {
+        int e = first + j;
+        int bi, bj;
+        if (herm) {
+            int r = 0;
+            while (r < nb1 && e >= nb1 - r) {
+                e -= nb1 - r;
+                ++r;
+            }
+            bi = r;
+            bj = r + e;
+        } else {
+            bi = e / nb2;
+            bj = e % nb2;
+        }
+        ra[j] = (unsigned)(((2 * bi) * 128 + lane) * 8);
+        rb[j] = (unsigned)(((same ? 0 : 2 * W8BUF) + (2 * bj) * 128 + lane) * 8);
+    }
+    d4 acc[W8T];
+#pragma unroll
+    for (int j = 0; j < W8T; ++j) acc[j] = d4{0, 0, 0, 0};
+    // the blocks this wave loads each chunk: q = wave + 16 i; A blocks first (2 per column
+    // block), then B's.  Column pointers are fixed; padding columns repeat the last column
+    // (they only reach outputs that are not stored)
+    const int nqa = 2 * nb1, nq = nqa + (same ? 0 : 2 * nb2);
+    const double2* colp[4];
+    unsigned ldsq[4];                 // LDS byte offset of block q, buffer 0
+    int rowoff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = wave + 16 * i;
+        colp[i] = nullptr;
+        ldsq[i] = 0;
+        rowoff[i] = 0;
+        if (q < nq) {
+            const bool isa = q < nqa;
+            const int qq = isa ? q : q - nqa;
+            const int cb = qq >> 1, rh = qq & 1;
+            const int mm = isa ? m1 : m2;
+            int col = 8 * cb + (lane & 7);
+            if (col >= mm) col = mm - 1;
+            colp[i] = isa ? seg_col(A, col, lda) : seg_col(B, col, ldb);
+            ldsq[i] = (unsigned)(((isa ? 0 : 2 * W8BUF) + (2 * cb + rh) * 128) * 8);
+            rowoff[i] = 8 * rh + (lane >> 3);
+        }
+    }
+    char* lbase = reinterpret_cast<char*>(lds);
+    auto issue = [&](long long kc, int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (wave + 16 * i < nq) {            // wave-uniform
+                long long row = kc + rowoff[i];
+                if (row >= k1) row = k1 - 1;
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(colp[i] + row),
+                    (__attribute__((address_space(3))) void*)(lbase + ldsq[i] + buf * (W8BUF * 8)), 16, 0, 0);
+            }
+        }
+    };
+    // rows of a partial chunk past k1: zero the slots this lane loaded (after its loads landed)
+    auto zero_tail = [&](long long kc, int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (wave + 16 * i < nq && kc + rowoff[i] >= k1)
+                *reinterpret_cast<double2*>(lbase + ldsq[i] + buf * (W8BUF * 8) + 16 * lane) = double2{0, 0};
+    };
+    auto step = [&](long long kc, auto bufc) {
+        constexpr int BUF = decltype(bufc)::value;
+        __builtin_amdgcn_s_waitcnt(0x3F70);      // vmcnt(0): this wave's loads of the chunk landed
+        if (kc + GKC > k1) zero_tail(kc, BUF);
+        __syncthreads();                         // every wave's loads landed; the other buffer is free
+        if (kc + GKC < k1) issue(kc + GKC, BUF ^ 1);
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < GKC; ks += 4) {
+            // row half ks / 8 (blocks 1 KiB apart), rows ks % 8 .. + 3 (128 bytes each)
+            const unsigned off = BUF * (W8BUF * 8) + (ks >> 3) * 1024 + (ks & 7) * 128;
+#pragma unroll
+            for (int j = 0; j < W8T; ++j) {
+                if (j < cnt) {            // wave-uniform
+                    const double av = *reinterpret_cast<const double*>(lbase + ra[j] + off);
+                    const double bv = *reinterpret_cast<const double*>(lbase + rb[j] + off);
+                    acc[j] = mfma(av, bv, acc[j]);
+                }
+            }
+        }
+        __builtin_amdgcn_s_setprio(0);
+    };
+    if (k0 < k1) issue(k0, 0);
+    for (long long kc = k0; kc < k1; kc += 2 * GKC) {
+        step(kc, std::integral_constant<int, 0>{});
+        if (kc + GKC >= k1) break;
+        step(kc + GKC, std::integral_constant<int, 1>{});
+    }
+    // register r of lane l holds D[4 r + l / 16][l % 16]: real row 16 bi + 4 r + l / 16,
+    // real column 16 bj + l % 16 (bi, bj recovered from the read addresses)
+#pragma unroll
+    for (int j = 0; j < W8T; ++j) {
+        if (j >= cnt) continue;
+        const int bi = (int)((ra[j] / 8 - lane) / 256);
+        const int bj = (int)(((rb[j] / 8 - lane) - (same ? 0 : 2 * W8BUF)) / 256);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * bi + 4 * r + (lane >> 4);
+            const int q = 16 * bj + (lane & 15);
             if (p < 2 * m1 && q < 2 * m2) out[(long long)q * ldr + p] = acc[j][r];
         }
     }
@@ -1276,7 +1418,12 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
         const long long kper = gram_rows_per_split(K, 1, 2LL * c->ncu, &nsplit, max_split);
         void* ws = nullptr;
         BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * r1 * r2 * sizeof(double), &ws));
-        if (w8)
+        // the same tiles and summation order either way: 2 loads straight to LDS, 1 stages
+        // through registers
+        if (w8 && c->gram_w8 == 2)
+            hipLaunchKernelGGL(k_gram_pair_w8d, dim3((unsigned)nsplit), dim3(1024), 0, c->stream, K, m1, m2,
+                               hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
+        else if (w8)
             hipLaunchKernelGGL(k_gram_pair_w8, dim3((unsigned)nsplit), dim3(1024), 0, c->stream, K, m1, m2,
                                hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
         else

@@ -238,6 +238,33 @@ def test_gram_pair_matches_numpy(K, m1, m2, sym):
     ctx.close()
 
 
+# The whole-matrix paired Gram in blocks of 8 complex columns loads its operands straight
+# into LDS (BDG_GRAM_W8=2, the default) or stages them through registers (1): the same tiles
+# and the same summation order, so the two must agree bit for bit (ragged tails included).
+@pytest.mark.parametrize("K,m1,m2,sym", [(20000, 120, 120, 2), (4099, 128, 128, 1), (777, 97, 97, 2),
+                                         (30011, 33, 100, 0), (50003, 100, 100, 2)])
+def test_gram_pair_w8_direct_matches_staged(K, m1, m2, sym, monkeypatch):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"gram pair w8 direct vs staged K={K} {m1}x{m2} sym={sym}")
+    A = W.random_block((m1, K), seed=1)
+    B = A if sym == 1 else (A * np.random.default_rng(3).uniform(0.5, 2.0, K)[None, :] if sym == 2
+                            else W.random_block((m2, K), seed=2))
+    Ad = torch.from_numpy(A).cuda()
+    Bd = Ad if sym == 1 else torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    out = {}
+    for mode in ("1", "2"):
+        monkeypatch.setenv("BDG_GRAM_W8", mode)
+        ctx = _ctx()
+        C = torch.zeros((2 * m2, 2 * m1), dtype=torch.complex128, device="cuda")
+        st = ctx._lib.bdg_test_gram_pair(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 1.0, _p(C), 2 * m1,
+                                         1 if sym else 0)
+        assert st == _lib.BDG_OK
+        out[mode] = C.cpu().numpy()
+        ctx.close()
+    assert np.array_equal(out["1"], out["2"])
+
+
 # One-pass update of the eigensolver (F columns first): the solve's shape, a ragged row tail,
 # no F part, no [W, P] part, and the widest block it takes (96 real columns)
 @pytest.mark.parametrize("K,m,mF,nb", [(5000, 120, 40, 80), (777, 24, 8, 16), (300, 16, 0, 10), (513, 16, 16, 6),
