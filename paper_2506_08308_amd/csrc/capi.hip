@@ -259,6 +259,7 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     c->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     if (const char* e = std::getenv("BDG_APPLY_CHUNK_MB")) c->apply_chunk_bytes = (size_t)std::atoll(e) << 20;
     if (const char* e = std::getenv("BDG_APPLY_PLANES")) c->apply_planes = e[0] != '0';
+    if (const char* e = std::getenv("BDG_APPLY_PLANES64")) c->apply_planes64 = e[0] != '0';
     if (const char* e = std::getenv("BDG_GRAM_WIDE")) c->gram_wide = e[0] != '0';
     if (const char* e = std::getenv("BDG_GRAM_W8")) c->gram_w8 = std::atoi(e);
     c->dim = pr->dim;

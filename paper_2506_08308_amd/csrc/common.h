@@ -78,6 +78,7 @@ struct bdg_ctx {
     // complex64 (f, g) operator on 128 x 128 x nz grids by xy-plane passes in LDS (three
     // passes over HBM instead of five)
     bool apply_planes = true;
+    bool apply_planes64 = true;   // ... and the complex128 form (two half-planes per plane)
     // symmetric paired Grams of 65..128 complex columns by one workgroup per K-split
     bool gram_wide = true;
     int gram_w8 = 2;              // ... in blocks of 8 complex columns (2: operands loaded straight to

@@ -81,8 +81,9 @@ template <int N> constexpr int contiguous_sync() { return N / 4 <= 64 ? SYNC_WAV
 
 // In-line FFT of length N.  On entry v[r] = x[i + r N/4]; on exit v[r] = X[i + r N/4].
 // lds(e) = lds[lb + e * ls] is this line's exchange buffer.  With SYNC_BLOCK every thread of
-// the block must call it (barriers), including threads whose line is out of range.
-template <typename V, int N, bool INV, int SYNC = SYNC_BLOCK>
+// the block must call it (barriers), including threads whose line is out of range.  tw holds
+// the N TWS twiddles of a transform TWS times longer (read at stride TWS).
+template <typename V, int N, bool INV, int SYNC = SYNC_BLOCK, int TWS = 1>
 __device__ __forceinline__ void line_fft(V v[4], int i, V* __restrict__ lds, int lb, int ls,
                                          const V* __restrict__ tw) {
     constexpr int Q = N / 4;
@@ -96,7 +97,7 @@ __device__ __forceinline__ void line_fft(V v[4], int i, V* __restrict__ lds, int
         if (s > 0) {
             const int step = N / (4 * p);
 #pragma unroll
-            for (int r = 1; r < 4; ++r) v[r] = mul_tw<V, INV>(v[r], tw[r * k * step]);
+            for (int r = 1; r < 4; ++r) v[r] = mul_tw<V, INV>(v[r], tw[r * k * step * TWS]);
         }
         dft4<V, INV>(v);
         const bool last = (s == NP4 - 1) && !R2;
@@ -112,8 +113,8 @@ __device__ __forceinline__ void line_fft(V v[4], int i, V* __restrict__ lds, int
     }
     if (R2) {
         // final radix-2 pass (span N/2): butterflies i and i + N/4
-        v[2] = mul_tw<V, INV>(v[2], tw[i]);
-        v[3] = mul_tw<V, INV>(v[3], tw[i + Q]);
+        v[2] = mul_tw<V, INV>(v[2], tw[i * TWS]);
+        v[3] = mul_tw<V, INV>(v[3], tw[(i + Q) * TWS]);
         V a0 = cadd(v[0], v[2]), a2 = csub(v[0], v[2]);
         V a1 = cadd(v[1], v[3]), a3 = csub(v[1], v[3]);
         v[0] = a0; v[1] = a1; v[2] = a2; v[3] = a3;
@@ -605,6 +606,189 @@ __global__ void __launch_bounds__(1024) k_plane_inv_couple(FieldAddr<const float
     }
 }
 
+// ----------------------------------------------------------------------------------------
+// xy-plane passes in complex128 (nx = ny = 128, 3-D).  A complex128 plane (256 KiB) does not
+// fit the LDS, so the y transform is split by decimation in frequency into two half-planes
+// of 64 rows (128 KiB each, transformed in LDS one after the other):
+//   P0[r] = A[r] + A[r + 64],  P1[r] = (A[r] - A[r + 64]) w^r   (r < 64, w = e^(-2 pi i/128)),
+// whose 64-point y transforms are the rows 2m and 2m + 1 of the 128-point one.  The kernels
+// run 512 threads (the half-plane transforms need about 90 registers, and P1 or the even
+// half's result waits in registers meanwhile); a thread holds column t % 128, rows
+// t / 128 + 4 j (j < 32) of a plane, so rows r and r + 64 are both its own.  The inverse pass inverts the even and the odd spectrum rows as half-planes and
+// combines them in registers, y[r] = E[r] + w^-r O[r], y[r + 64] = E[r] - w^-r O[r], before
+// the coupling.  Fields, tasks and the half swap are those of the complex64 kernels.
+// ----------------------------------------------------------------------------------------
+constexpr int PLH = PLN / 2;
+constexpr size_t HALF64_LDS = (size_t)PLH * PLP * sizeof(double2);
+
+// MODE 0: the 64 rows (128-point x transforms, 32 lanes per line); MODE 1: the 128 columns
+// (64-point y transforms, 16 lanes per line, the 128-point table at stride 2).  Lines lie on
+// consecutive lanes of one wave; one workgroup barrier at the end.
+constexpr int P64T = 512;                         // threads of the complex128 plane kernels
+// compiler barrier: bounds how far the unrolled loops below hoist their loads (all of them
+// in flight at once would not fit the registers)
+__device__ __forceinline__ void hoist_fence() { asm volatile("" ::: "memory"); }
+template <bool INV, int MODE>
+__device__ __forceinline__ void half_lines(double2* pl, const double2* __restrict__ tw) {
+    constexpr int NL = MODE == 0 ? PLN : PLH;
+    constexpr int Q = NL / 4;
+    constexpr int NLINES = MODE == 0 ? PLH : PLN;
+    constexpr int LPR = P64T / Q;
+    const int t = threadIdx.x;
+    const int ln = t / Q, i = t % Q;
+#pragma unroll 1
+    for (int rnd = 0; rnd < NLINES / LPR; ++rnd) {
+        const int line = rnd * LPR + ln;
+        const int lb = MODE == 0 ? line * PLP : line;
+        const int ls = MODE == 0 ? 1 : PLP;
+        // the twiddle loads stay in this round (hoisted out of the kernel's loops, the float64
+        // twiddles of every stage would stay live in registers)
+        const double2* twr = tw;
+        asm volatile("" : "+s"(twr));
+        double2 v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = pl[lb + (i + r * Q) * ls];
+        line_fft<double2, NL, INV, SYNC_WAVE, (MODE == 0 ? 1 : 2)>(v, i, pl, lb, ls, twr);
+        fft_sync<SYNC_WAVE>();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pl[lb + (i + r * Q) * ls] = v[r];
+    }
+    lds_barrier();
+}
+
+// forward: workgroup w = (field f, plane z); Y[sigma(f)] plane z = F_xy X[f] plane z.  One
+// plane per workgroup (a persistent loop would keep the unrolled loops' address arithmetic
+// live across planes, more than the registers hold)
+__global__ void __launch_bounds__(P64T) k_plane_fwd64(FieldAddr<const double2> in, FieldAddr<double2> out,
+                                                     long long nfields, int nz, const double2* __restrict__ twx,
+                                                     const double2* __restrict__ twy) {
+    extern __shared__ double2 ph[];
+    const long long ntask = nfields * nz;
+    const long long w = blockIdx.x;
+    if (w >= ntask) return;
+    const int t = threadIdx.x;
+    const int r0 = t >> 7, c = t & 127;
+    {
+        const double2* src = in.field(w / nz) + (w % nz) * (long long)(PLN * PLN);
+        const long long f = w / nz;
+        const long long vec = f / 6;
+        const int s = (int)(f % 6);
+        const int so = s < 3 ? s + 3 : s - 3;
+        double2* dst = out.field(vec * 6 + so) + (w % nz) * (long long)(PLN * PLN);
+        double2 p1[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int r = r0 + 4 * j;
+            const double2 a = src[r * PLN + c], b = src[(r + PLH) * PLN + c];
+            ph[r * PLP + c] = cadd(a, b);
+            p1[j] = mul_tw<double2, false>(csub(a, b), twy[r]);
+            if ((j & 3) == 3) hoist_fence();
+        }
+        lds_barrier();
+        half_lines<false, 0>(ph, twx);
+        half_lines<false, 1>(ph, twy);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = t + P64T * j;        // half-plane row e / 128 -> plane row 2 (e / 128)
+            dst[(2 * (e >> 7)) * PLN + (e & 127)] = ph[(e >> 7) * PLP + (e & 127)];
+            if ((j & 3) == 3) hoist_fence();
+        }
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) ph[(r0 + 4 * j) * PLP + c] = p1[j];
+        lds_barrier();
+        half_lines<false, 0>(ph, twx);
+        half_lines<false, 1>(ph, twy);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = t + P64T * j;
+            dst[(2 * (e >> 7) + 1) * PLN + (e & 127)] = ph[(e >> 7) * PLP + (e & 127)];
+            if ((j & 3) == 3) hoist_fence();
+        }
+        lds_barrier();
+    }
+}
+
+// inverse + coupling in complex128, tasks as in k_plane_inv_couple (in place on Y), one task per
+// workgroup: the grid has a workgroup per task, dealt to the XCDs as there
+template <int TRANS>
+__global__ void __launch_bounds__(P64T) k_plane_inv_couple64(FieldAddr<const double2> xin, FieldAddr<double2> yio,
+                                                             long long nvec, int nz,
+                                                             const double2* __restrict__ twx,
+                                                             const double2* __restrict__ twy,
+                                                             const double* __restrict__ coef) {
+    extern __shared__ double2 ph[];
+    const long long ngroups = nvec * 2 * nz;
+    const int nxcd = 8, xcd = blockIdx.x % nxcd;
+    const int nslot = (gridDim.x - xcd + nxcd - 1) / nxcd;
+    const int slot = blockIdx.x / nxcd;
+    const long long g0 = ngroups * xcd / nxcd, g1 = ngroups * (xcd + 1) / nxcd;
+    const long long ntask = 3 * (g1 - g0);
+    long long u = slot;
+    if (u >= ntask) return;
+    const int t = threadIdx.x;
+    const int r0 = t >> 7, c = t & 127;
+    const long long npts = xin.npts;
+    auto sidx = [](int r, int c2) {
+        const int lo = r < c2 ? r : c2, hi = r < c2 ? c2 : r;
+        return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+    };
+    // spectrum rows 2m + half of the plane -> LDS half-plane, inverse y then x, this thread's
+    // rows r0 + 8 j back into registers
+    auto inv_half = [&](const double2* io, int half, double2 (&res)[16]) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = t + P64T * j;
+            ph[(e >> 7) * PLP + (e & 127)] = io[(2 * (e >> 7) + half) * PLN + (e & 127)];
+            if ((j & 7) == 7) hoist_fence();
+        }
+        lds_barrier();
+        half_lines<true, 1>(ph, twy);
+        half_lines<true, 0>(ph, twx);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) res[j] = ph[(r0 + 4 * j) * PLP + c];
+        lds_barrier();
+    };
+    {
+        const long long g = g0 + u / 3;
+        const int a = (int)(u % 3);
+        const int h = (int)(g % 2);
+        const long long vec = (g / 2) % nvec;
+        const long long z = g / (2 * nvec);
+        const long long poff = z * (long long)(PLN * PLN);
+        double2* io = yio.field(vec * 6 + 3 * h + a) + poff;
+        double2 ev[16], od[16];
+        inv_half(io, 0, ev);
+        inv_half(io, 1, od);
+        const int hin = 1 - h;
+        const bool plus = (h == 1) != (TRANS != 0);
+        const double* cb = coef + (plus ? 0 : 6) * npts + poff;
+        const double* c0 = cb + sidx(a, 0) * npts;
+        const double* c1 = cb + sidx(a, 1) * npts;
+        const double* c2 = cb + sidx(a, 2) * npts;
+        const double2* x0 = xin.field(vec * 6 + 3 * hin + 0) + poff;
+        const double2* x1 = xin.field(vec * 6 + 3 * hin + 1) + poff;
+        const double2* x2 = xin.field(vec * 6 + 3 * hin + 2) + poff;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j & 1) hoist_fence();
+            const double2 o = mul_tw<double2, true>(od[j], twy[r0 + 4 * j]);
+            const double2 kk2[2] = {cadd(ev[j], o), csub(ev[j], o)};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = (r0 + 4 * j + PLH * q) * PLN + c;     // row r0 + 4 j + 64 q
+                const double2 kk = kk2[q];
+                const double m0 = c0[e], m1 = c1[e], m2 = c2[e];
+                const double2 u0 = x0[e], u1 = x1[e], u2 = x2[e];
+                double2 y;
+                y.x = kk.x + m0 * u0.x + m1 * u1.x + m2 * u2.x;
+                y.y = kk.y + m0 * u0.y + m1 * u1.y + m2 * u2.y;
+                io[e] = y;
+            }
+        }
+    }
+}
+
 template <typename V> FieldAddr<V> fa_block(V* lo, V* hi, long long vstride, long long npts) {
     FieldAddr<V> a; a.lo = lo; a.hi = hi; a.vstride = vstride; a.fpv = 6; a.npts = npts; return a;
 }
@@ -753,6 +937,35 @@ bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAd
     return hip_check(c, hipGetLastError(), "k_plane_inv_couple");
 }
 
+// the three-pass (f, g) operator of complex128 128 x 128 x nz grids (see k_plane_fwd64)
+template <int TRANS>
+bdg_status apply_planes64(bdg_ctx* c, int nvec, FieldAddr<const double2> X, FieldAddr<double2> Y, MultSpec ms) {
+    static bool lds_set = false;
+    if (!lds_set) {
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_fwd64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)HALF64_LDS));
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple64<0>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)HALF64_LDS));
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple64<1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)HALF64_LDS));
+        lds_set = true;
+    }
+    const long long nf = 6LL * nvec;
+    const int nz = c->n[2];
+    const long long ntask = nf * nz;
+    hipLaunchKernelGGL(k_plane_fwd64, dim3((unsigned)ntask), dim3(P64T), HALF64_LDS, c->stream, X, Y, nf, nz,
+                       (const double2*)c->tw64[0], (const double2*)c->tw64[1]);
+    BDG_TRY(hip_check(c, hipGetLastError(), "k_plane_fwd64"));
+    BDG_TRY((run_strided<double2, false, 1>(c, Y, nf, 2, ms)));
+    // one workgroup per task: each XCD's share of the 2 nvec nz groups, three tasks each, plus
+    // a workgroup of slack per XCD for the rounding of the shares
+    const unsigned grid_inv = (unsigned)(8 * (3 * ((2 * (long long)nvec * nz + 7) / 8) + 3));
+    hipLaunchKernelGGL(k_plane_inv_couple64<TRANS>, dim3(grid_inv), dim3(P64T), HALF64_LDS, c->stream, X, Y,
+                       (long long)nvec, nz, (const double2*)c->tw64[0], (const double2*)c->tw64[1],
+                       (const double*)c->coef64);
+    return hip_check(c, hipGetLastError(), "k_plane_inv_couple64");
+}
+
 template <typename V, int FORM, int TRANS>
 bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> Y) {
     MultSpec ms = make_ms(c, 0, 0.0);
@@ -760,6 +973,10 @@ bdg_status apply_chunk(bdg_ctx* c, int nvec, FieldAddr<const V> X, FieldAddr<V> 
     if constexpr (std::is_same<V, float2>::value && FORM == 1) {
         if (c->apply_planes && c->dim == 3 && c->n[0] == PLN && c->n[1] == PLN)
             return apply_planes<TRANS>(c, nvec, X, Y, Y, ms);
+    }
+    if constexpr (std::is_same<V, double2>::value && FORM == 1) {
+        if (c->apply_planes64 && c->dim == 3 && c->n[0] == PLN && c->n[1] == PLN)
+            return apply_planes64<TRANS>(c, nvec, X, Y, ms);
     }
     if (c->dim == 1) return run_couple<V, FORM, TRANS, true>(c, X, Y, nvec, ms);
     BDG_TRY((run_xpass<V, false, 0>(c, X, Y, nf, ms)));

@@ -118,6 +118,42 @@ def test_apply_fp32_plane_passes_match_oracle(transpose, monkeypatch):
     monkeypatch.delenv("BDG_APPLY_PLANES")
 
 
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_apply_fp64_half_plane_passes_match_oracle(transpose, monkeypatch):
+    """complex128 (f, g) operator on a 128 x 128 x nz grid: the three-pass form (each xy plane
+    as two half-planes in LDS) against the oracle, and against the five-pass form."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Form, Precision
+    w = PLANE_CASE
+    say(f"apply fp64 half-planes {w.name} T={transpose}")
+    V = W.potential(w)
+    phi, mu = W.initial_spinor(w), np.array([1.0, 0.9, 1.1])
+    coef = bdg.coefficients(phi, mu, V, w.beta_n, w.beta_s)
+    X = W.random_block((3, 6) + w.shape, seed=19)
+    outs = []
+    for planes in ("1", "0"):
+        monkeypatch.setenv("BDG_APPLY_PLANES64", planes)
+        ctx = make_ctx(w, Precision.FP64, V)
+        ctx.set_ground_state(torch.from_numpy(phi), mu)
+        outs.append(ctx.apply(torch.from_numpy(X).to("cuda"), Form.FG, bool(transpose)).cpu().numpy())
+        ctx.close()
+    if transpose:
+        Hp, Hm = bdg.hpm(coef)
+        from oracle import spectral
+        f, g = X[:, :3], X[:, 3:]
+        ref = np.concatenate([spectral.kinetic_apply(g, w.n, w.L) + bdg._pw(Hp, g),
+                              spectral.kinetic_apply(f, w.n, w.L) + bdg._pw(Hm, f)], axis=1)
+    else:
+        ref = bdg.apply_fg(coef, X, w.n, w.L)
+    scale = np.abs(ref).max()
+    err = np.abs(outs[0] - ref).max() / scale
+    cross = np.abs(outs[0] - outs[1]).max() / scale
+    say(f"   rel err {err:.2e} (oracle), {cross:.2e} (five-pass form)")
+    assert err < 1e-13
+    assert cross < 1e-13
+    monkeypatch.delenv("BDG_APPLY_PLANES64")
+
+
 def test_apply_rejects_bad_arguments():
     torch = torch_cuda()
     from paper_2506_08308_amd import BdgError, Form, Precision
