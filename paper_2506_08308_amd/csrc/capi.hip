@@ -262,6 +262,7 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     if (const char* e = std::getenv("BDG_APPLY_PLANES64")) c->apply_planes64 = e[0] != '0';
     if (const char* e = std::getenv("BDG_GRAM_WIDE")) c->gram_wide = e[0] != '0';
     if (const char* e = std::getenv("BDG_GRAM_W8")) c->gram_w8 = std::atoi(e);
+    if (const char* e = std::getenv("BDG_JACOBI_SPLIT")) c->jacobi_split = std::max(1, std::min(8, std::atoi(e)));
     c->dim = pr->dim;
     c->npts = 1;
     c->hd = 1.0;

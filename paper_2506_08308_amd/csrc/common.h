@@ -83,8 +83,9 @@ struct bdg_ctx {
     bool gram_wide = true;
     int gram_w8 = 2;              // ... in blocks of 8 complex columns (2: operands loaded straight to
                                   // LDS, 1: staged through registers, 0: off)
+    int jacobi_split = 8;         // workgroups per column-block pair in a real Jacobi round
     // scratch owned by the context (grown on demand)
-    DevBuf scratch[8];
+    DevBuf scratch[9];
     // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out
     // 256-byte aligned pieces of it in order (nothing is allocated, ctx_free of a piece does
     // nothing) and the Gram launches keep their split-K partials within `gram_bytes`

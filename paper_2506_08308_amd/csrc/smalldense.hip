@@ -682,8 +682,13 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_g(int rows, int m, double
 // paired real form): real rotations (the phase e reduces to the sign of the off-diagonal
 // entry), staging of the real parts only (half the LDS), a quarter of the flops.  Staging
 // and the V rows keep several loads in flight per thread: the round is latency-bound.
+// gridDim.y workgroups share a pair: each stages the pair and computes the same rotation
+// (same inputs, same operations), and applies it to every gridDim.y-th block of 16 rows.
+// With more than one, the round reads Gin, Vin and writes Gout, Vout (other buffers), so
+// that no workgroup stages rows another one has already rotated; with one they may alias.
 template <int W>
-__global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double2* G, int ldg, double2* V, int ldv,
+__global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, const double2* Gin, int ldg,
+                                                         const double2* Vin, int ldv, double2* Gout, double2* Vout,
                                                          int nblk, int rnd, const double* __restrict__ frob2,
                                                          int* rotations, double conv) {
     constexpr int N2 = 2 * W, PA = N2 + 1, TPC = 256 / N2, U = 8;
@@ -710,7 +715,7 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
         // TPC threads per column, U loads in flight per thread
         const int kc = t / TPC, lane = t % TPC;
         const bool vk = valid(kc);
-        const double2* src = G + (long long)(vk ? colidx(kc) : 0) * ldg;
+        const double2* src = Gin + (long long)(vk ? colidx(kc) : 0) * ldg;
         for (int i0 = lane; i0 < rows; i0 += U * TPC) {
             double v[U];
 #pragma unroll
@@ -806,7 +811,7 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
         const int wave = t >> 6, lane = t & 63;
         const int li = lane & 15, lk = lane >> 4;
         const int nrb = (rows + m + 15) / 16;
-        for (int rb = wave; rb < nrb; rb += 4) {
+        for (int rb = wave + 4 * (int)blockIdx.y; rb < nrb; rb += 4 * (int)gridDim.y) {
             const int row = 16 * rb + li;                  // this lane's A row
             const bool rg = row < rows;
             const bool rv = !rg && row < rows + m;
@@ -817,7 +822,7 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
             for (int kc = 0; kc < N2 / 4; ++kc) {
                 const int kk = 4 * kc + lk;
                 const double a = rg ? lg[kk * pg + row]
-                                    : ((rv && valid(kk)) ? V[(long long)colidx(kk) * ldv + (row - rows)].x : 0.0);
+                                    : ((rv && valid(kk)) ? Vin[(long long)colidx(kk) * ldv + (row - rows)].x : 0.0);
 #pragma unroll
                 for (int cb = 0; cb < (N2 + 15) / 16; ++cb) {
                     const int cc = 16 * cb + li;
@@ -832,13 +837,14 @@ __global__ void __launch_bounds__(256) k_bjacobi_round_r(int rows, int m, double
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int orow = 16 * rb + 4 * r + lk;
-                    if (orow < rows) G[(long long)colidx(cc) * ldg + orow] = mkc(acc[cb][r], 0.0);
-                    else if (orow < rows + m) V[(long long)colidx(cc) * ldv + (orow - rows)] = mkc(acc[cb][r], 0.0);
+                    if (orow < rows) Gout[(long long)colidx(cc) * ldg + orow] = mkc(acc[cb][r], 0.0);
+                    else if (orow < rows + m)
+                        Vout[(long long)colidx(cc) * ldv + (orow - rows)] = mkc(acc[cb][r], 0.0);
                 }
             }
         }
     }
-    if (t == 0 && rot_any) atomicAdd(rotations, 1);
+    if (t == 0 && rot_any && blockIdx.y == 0) atomicAdd(rotations, 1);
 }
 
 // column norms of G (rows x m) into s; permutation to descending order (stable), applied to
@@ -980,16 +986,35 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
                             : (w == 16 ? (const void*)k_bjacobi_round_g<16>
                                : w == 8 ? (const void*)k_bjacobi_round_g<8> : (const void*)k_bjacobi_round_g<4>);
     BDG_HIP(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // real rounds: nsplit workgroups per pair (the rotation computed by each, the rows shared
+    // out); with nsplit > 1 the rounds alternate between (G, V) and a second copy
+    int nsplit = 1;
+    double2* Gb[2] = {G, G};
+    double2* Vb[2] = {V, V};
+    if (real && !c->arena.base && c->jacobi_split > 1) {
+        nsplit = c->jacobi_split;
+        void* pp = nullptr;
+        BDG_TRY(ctx_scratch(c, 8, ((size_t)ldg * m + (size_t)ldv * m) * sizeof(double2), &pp));
+        Gb[1] = (double2*)pp;
+        Vb[1] = Gb[1] + (size_t)ldg * m;
+    }
+    int cur = 0;
 #define BDG_ROUND(KN, WV)                                                                                         \
     hipLaunchKernelGGL(KN<WV>, dim3(nblk / 2), dim3(256), lds, c->stream, rows, m, G, ldg, V, ldv, nblk, rnd,   \
+                       (const double*)frob2, counter, conv)
+#define BDG_ROUND_R(WV)                                                                                           \
+    hipLaunchKernelGGL(k_bjacobi_round_r<WV>, dim3(nblk / 2, nsplit), dim3(256), lds, c->stream, rows, m,       \
+                       (const double2*)Gb[cur], ldg, (const double2*)Vb[cur], ldv,                              \
+                       Gb[nsplit > 1 ? cur ^ 1 : cur], Vb[nsplit > 1 ? cur ^ 1 : cur], nblk, rnd,              \
                        (const double*)frob2, counter, conv)
     for (int sweep = 0; sweep < 40; ++sweep) {
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, counter);
         for (int rnd = 0; rnd < nblk - 1; ++rnd) {
             if (real) {
-                if (w == 16) BDG_ROUND(k_bjacobi_round_r, 16);
-                else if (w == 8) BDG_ROUND(k_bjacobi_round_r, 8);
-                else BDG_ROUND(k_bjacobi_round_r, 4);
+                if (w == 16) BDG_ROUND_R(16);
+                else if (w == 8) BDG_ROUND_R(8);
+                else BDG_ROUND_R(4);
+                if (nsplit > 1) cur ^= 1;
             } else {
                 if (w == 16) BDG_ROUND(k_bjacobi_round_g, 16);
                 else if (w == 8) BDG_ROUND(k_bjacobi_round_g, 8);
@@ -1003,6 +1028,13 @@ bdg_status small_svd(bdg_ctx* c, int rows, int m, double2* G, int ldg, double2* 
         if (h == 0) break;
     }
 #undef BDG_ROUND
+#undef BDG_ROUND_R
+    if (cur == 1) {
+        BDG_HIP(c, hipMemcpy2DAsync(G, (size_t)ldg * sizeof(double2), Gb[1], (size_t)ldg * sizeof(double2),
+                                    (size_t)rows * sizeof(double2), (size_t)m, hipMemcpyDeviceToDevice, c->stream));
+        BDG_HIP(c, hipMemcpy2DAsync(V, (size_t)ldv * sizeof(double2), Vb[1], (size_t)ldv * sizeof(double2),
+                                    (size_t)m * sizeof(double2), (size_t)m, hipMemcpyDeviceToDevice, c->stream));
+    }
     void* ws = nullptr;
     BDG_TRY(ctx_scratch(c, 1, ((size_t)rows * m + (size_t)m * m) * sizeof(double2), &ws));
     hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, c->stream, rows, m, G, ldg, V, ldv, s, (double2*)ws,
