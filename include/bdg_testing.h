@@ -33,6 +33,13 @@ bdg_status bdg_test_update(bdg_ctx* ctx, long long K, int m, const void* S, long
 bdg_status bdg_test_gram_pair(bdg_ctx* ctx, long long K, int m1, int m2, const void* A, long long lda,
                               const void* B, long long ldb, double alpha, void* C, int ldc, int symmetric);
 
+/* The kinetic-potential preconditioner D (|k|^2/2 + sigma)^-1 D (Section 2.3) as the mixed
+ * solve applies it: X32 (nvec complex64 vectors of six fields, npts points each, contiguous)
+ * in float32, the result widened into Y64 (complex128, the same layout).  X32 is used as
+ * work space and overwritten.  Needs the ground state (bdg_set_ground_state or
+ * bdg_ground_state), which fixes D and sigma.  BDG_ESTATE without it. */
+bdg_status bdg_test_precond_mixed(bdg_ctx* ctx, int nvec, void* X32, void* Y64);
+
 /* Paired real form: Y (nb real columns = nb / 2 complex columns, ldy) = S (2 m real columns =
  * m complex columns, lds) * Cm (2 m x nb real coefficients stored as complex, only the real
  * parts are read, ldcm >= 2 m) + beta * Y; nb even. */

@@ -18,7 +18,7 @@ EXPORTS = ("bdg_create", "bdg_destroy", "bdg_last_error", "bdg_ground_state", "b
            "bdg_perturbed_density", "bdg_stats", "bdg_biortho_noalloc",
            "bdg_mode_amplitudes",
            "bdg_test_gram", "bdg_test_update", "bdg_test_svd", "bdg_test_svd_real", "bdg_test_cholesky", "bdg_test_pchol",
-           "bdg_test_plu", "bdg_test_gram_pair", "bdg_test_update_pair",
+           "bdg_test_plu", "bdg_test_gram_pair", "bdg_test_update_pair", "bdg_test_precond_mixed",
            "bdg_test_update_pair_fused")
 
 
@@ -77,6 +77,8 @@ def load() -> ctypes.CDLL:
     lib.bdg_test_gram_pair.argtypes = [vp, ll, i, i, vp, ll, vp, ll, d, vp, i, i]
     lib.bdg_test_gram_pair.restype = st
     lib.bdg_test_update_pair.argtypes = [vp, ll, i, vp, ll, vp, i, i, d, vp, ll]
+    lib.bdg_test_precond_mixed.argtypes = [vp, i, vp, vp]
+    lib.bdg_test_precond_mixed.restype = st
     lib.bdg_test_update_pair.restype = st
     lib.bdg_test_svd.argtypes = [vp, i, i, vp, i, vp, i, vp]
     lib.bdg_test_svd.restype = st

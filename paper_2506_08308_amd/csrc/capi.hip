@@ -455,6 +455,16 @@ bdg_status bdg_test_gram_pair(bdg_ctx* c, long long K, int m1, int m2, const voi
     return BDG_OK;
 }
 
+bdg_status bdg_test_precond_mixed(bdg_ctx* c, int nvec, void* X32, void* Y64) {
+    if (!c || !X32 || !Y64 || nvec < 1) return ctx_fail(c, BDG_EINVAL, "bad args");
+    const long long np = c->npts;
+    BlockRef<float2> x{(float2*)X32, (float2*)X32 + 3 * np, 6 * np};
+    BlockRef<double2> y{(double2*)Y64, (double2*)Y64 + 3 * np, 6 * np};
+    BDG_TRY(launch_precond_mixed(c, nvec, x, y));
+    BDG_HIP(c, hipStreamSynchronize(c->stream));
+    return BDG_OK;
+}
+
 bdg_status bdg_test_update_pair(bdg_ctx* c, long long K, int m, const void* S, long long lds, const void* Cm, int ldcm,
                                 int nb, double beta, void* Y, long long ldy) {
     if (!c || !S || !Cm || !Y || K < 1 || m < 1 || nb < 2 || (nb & 1) || ldcm < 2 * m)

@@ -492,10 +492,55 @@ __device__ __forceinline__ void plane_to_lds(float2* pl, const float2 (&v)[16]) 
     }
 }
 
-// forward: task w = (field f, plane z), f-major; Y[sigma(f)] plane z = F_xy X[f] plane z
+// forward: task w = (field f, plane z), f-major; Y[sigma(f)] plane z = F_xy X[f] plane z.
+// PREC (the preconditioner's first pass): Y[f] plane z = F_xy (w X[f]) plane z with the
+// pointwise weight w, no half swap (the transforms of the x and y passes it replaces)
+template <bool PREC = false>
 __global__ void __launch_bounds__(1024) k_plane_fwd(FieldAddr<const float2> in, FieldAddr<float2> out,
                                                    long long nfields, int nz, const float2* __restrict__ twx,
-                                                   const float2* __restrict__ twy) {
+                                                   const float2* __restrict__ twy,
+                                                   const float* __restrict__ wgt = nullptr) {
+    extern __shared__ float2 pl[];
+    const long long ntask = nfields * nz;
+    long long w = blockIdx.x;
+    if (w >= ntask) return;
+    const int t = threadIdx.x;
+    float2 v[16];
+    plane_load(v, in.field(w / nz) + (w % nz) * (long long)(PLN * PLN));
+    for (; w < ntask; w += gridDim.x) {
+        if constexpr (PREC) {
+            const float* wz = wgt + (w % nz) * (long long)(PLN * PLN);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], wz[t + 1024 * j]);
+        }
+        plane_to_lds(pl, v);
+        lds_barrier();
+        const long long wn = w + gridDim.x;
+        if (wn < ntask) plane_load(v, in.field(wn / nz) + (wn % nz) * (long long)(PLN * PLN));
+        plane_lines<false, 0>(pl, twx);
+        plane_lines<false, 1>(pl, twy);
+        const long long f = w / nz;
+        const long long vec = f / 6;
+        const int s = (int)(f % 6);
+        const int so = PREC ? s : (s < 3 ? s + 3 : s - 3);
+        float2* dst = out.field(vec * 6 + so) + (w % nz) * (long long)(PLN * PLN);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = t + 1024 * j;
+            dst[e] = pl[(e >> 7) * PLP + (e & 127)];
+        }
+        lds_barrier();       // the plane is read out of LDS before the next one is staged
+    }
+}
+
+// the preconditioner's last pass: task w = (field f, plane z); Y64[f] plane z =
+// w F_xy^-1 X[f] plane z (y then x inverse, the pointwise weight, widened to float64), the
+// transforms of the y and x inverse passes it replaces.  Persistent, the next plane's loads
+// in flight as in k_plane_fwd.
+__global__ void __launch_bounds__(1024) k_plane_inv_w(FieldAddr<const float2> in, FieldAddr<double2> out,
+                                                     long long nfields, int nz, const float2* __restrict__ twx,
+                                                     const float2* __restrict__ twy,
+                                                     const float* __restrict__ wgt) {
     extern __shared__ float2 pl[];
     const long long ntask = nfields * nz;
     long long w = blockIdx.x;
@@ -508,17 +553,16 @@ __global__ void __launch_bounds__(1024) k_plane_fwd(FieldAddr<const float2> in, 
         lds_barrier();
         const long long wn = w + gridDim.x;
         if (wn < ntask) plane_load(v, in.field(wn / nz) + (wn % nz) * (long long)(PLN * PLN));
-        plane_lines<false, 0>(pl, twx);
-        plane_lines<false, 1>(pl, twy);
-        const long long f = w / nz;
-        const long long vec = f / 6;
-        const int s = (int)(f % 6);
-        const int so = s < 3 ? s + 3 : s - 3;
-        float2* dst = out.field(vec * 6 + so) + (w % nz) * (long long)(PLN * PLN);
+        plane_lines<true, 1>(pl, twy);
+        plane_lines<true, 0>(pl, twx);
+        const long long poff = (w % nz) * (long long)(PLN * PLN);
+        double2* dst = out.field(w / nz) + poff;
+        const float* wz = wgt + poff;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int e = t + 1024 * j;
-            dst[e] = pl[(e >> 7) * PLP + (e & 127)];
+            const float2 y = cscale(pl[(e >> 7) * PLP + (e & 127)], wz[e]);
+            dst[e] = cmk<double2>(y.x, y.y);
         }
         lds_barrier();       // the plane is read out of LDS before the next one is staged
     }
@@ -912,7 +956,7 @@ bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAd
                         MultSpec ms) {
     static bool lds_set = false;
     if (!lds_set) {
-        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+        BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_fwd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)PLANE_LDS));
         BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_couple<0>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
@@ -926,8 +970,8 @@ bdg_status apply_planes(bdg_ctx* c, int nvec, FieldAddr<const float2> X, FieldAd
     const int nz = c->n[2];
     const long long ntask = nf * nz;
     const unsigned grid = (unsigned)std::min<long long>(ntask, c->ncu);
-    hipLaunchKernelGGL(k_plane_fwd, dim3(grid), dim3(1024), PLANE_LDS, c->stream, X, Y, nf, nz,
-                       (const float2*)c->tw32[0], (const float2*)c->tw32[1]);
+    hipLaunchKernelGGL(k_plane_fwd<false>, dim3(grid), dim3(1024), PLANE_LDS, c->stream, X, Y, nf, nz,
+                       (const float2*)c->tw32[0], (const float2*)c->tw32[1], (const float*)nullptr);
     BDG_TRY(hip_check(c, hipGetLastError(), "k_plane_fwd"));
     BDG_TRY((run_strided<float2, false, 1>(c, Y, nf, 2, ms)));
     const unsigned grid_inv = (unsigned)std::max<long long>(8, std::min<long long>(ntask, c->ncu));
@@ -1104,6 +1148,29 @@ bdg_status launch_precond_mixed(bdg_ctx* c, int nvec, BlockRef<float2> X32, Bloc
     FieldAddr<const float2> xc = fa_block<const float2>(X32.lo, X32.hi, X32.vstride, c->npts);
     FieldAddr<double2> ya = fa_block<double2>(Y64.lo, Y64.hi, Y64.vstride, c->npts);
     const float* wgt = c->pw32;
+    if (c->apply_planes && c->dim == 3 && c->n[0] == PLN && c->n[1] == PLN) {
+        // three passes: weighted xy forward in LDS, z with the multiplier, xy inverse weighted
+        // and widened (the x and y passes below, fused by planes; the weight's products round
+        // before the transforms here, where the x pass may contract them into its first
+        // butterflies)
+        static bool lds_set = false;
+        if (!lds_set) {
+            BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_fwd<true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLANE_LDS));
+            BDG_HIP(c, hipFuncSetAttribute((const void*)k_plane_inv_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)PLANE_LDS));
+            lds_set = true;
+        }
+        const int nz = c->n[2];
+        const unsigned grid = (unsigned)std::min<long long>(nf * nz, c->ncu);
+        hipLaunchKernelGGL(k_plane_fwd<true>, dim3(grid), dim3(1024), PLANE_LDS, c->stream, xc, xa, nf, nz,
+                           (const float2*)c->tw32[0], (const float2*)c->tw32[1], wgt);
+        BDG_TRY(hip_check(c, hipGetLastError(), "k_plane_fwd"));
+        BDG_TRY((run_strided<float2, false, 1>(c, xa, nf, 2, ms)));
+        hipLaunchKernelGGL(k_plane_inv_w, dim3(grid), dim3(1024), PLANE_LDS, c->stream, xc, ya, nf, nz,
+                           (const float2*)c->tw32[0], (const float2*)c->tw32[1], wgt);
+        return hip_check(c, hipGetLastError(), "k_plane_inv_w");
+    }
     if (c->dim == 1) return run_xpass<float2, false, 1, double2>(c, xc, ya, nf, ms, wgt);
     BDG_TRY((run_xpass<float2, false, 0>(c, xc, xa, nf, ms, wgt)));
     if (c->dim == 2) {

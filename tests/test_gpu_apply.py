@@ -75,6 +75,11 @@ def test_apply_fp32_matches_oracle(w):
     ctx.close()
 
 
+def _p(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
 PLANE_CASE = W.Workload("3d_128x128x8_fm", 3, (128, 128, 8), (8.0, 8.0, 2.0), "harmonic3_z2", 40.0, -0.5, 0.1)
 
 
@@ -152,6 +157,38 @@ def test_apply_fp64_half_plane_passes_match_oracle(transpose, monkeypatch):
     assert err < 1e-13
     assert cross < 1e-13
     monkeypatch.delenv("BDG_APPLY_PLANES64")
+
+
+@pytest.mark.parametrize("planes", ["1", "0"])
+def test_precond_mixed_matches_oracle(planes, monkeypatch):
+    """The mixed solve's preconditioner D (|k|^2/2 + sigma)^-1 D in float32 on a 128 x 128 x nz
+    grid: the three-pass plane form (planes = 1) and the five-pass form against the oracle."""
+    torch = torch_cuda()
+    from paper_2506_08308_amd import Precision, _lib
+    from oracle import lrep
+    w = PLANE_CASE
+    say(f"precond mixed {w.name} planes={planes}")
+    V = W.potential(w)
+    phi, mu = W.initial_spinor(w), np.array([1.0, 0.9, 1.1])
+    coef = bdg.coefficients(phi, mu, V, w.beta_n, w.beta_s)
+    X = W.random_block((3, 6) + w.shape, seed=23).astype(np.complex64)
+    monkeypatch.setenv("BDG_APPLY_PLANES", planes)
+    ctx = make_ctx(w, Precision.FP32_APPLY, V)
+    ctx.set_ground_state(torch.from_numpy(phi), mu)
+    Xd = torch.from_numpy(X.copy()).to("cuda")
+    Yd = torch.zeros(X.shape, dtype=torch.complex128, device="cuda")
+    assert ctx._lib.bdg_test_precond_mixed(ctx._h, X.shape[0], _p(Xd), _p(Yd)) == _lib.BDG_OK
+    got = Yd.cpu().numpy()
+    ctx.close()
+    monkeypatch.delenv("BDG_APPLY_PLANES")
+    sigma, D = lrep.preconditioner_parameters(V, mu)
+    prob = lrep.LrepProblem(coef, w.n, w.L, D)
+    npts = int(np.prod(w.shape))
+    cols = X.astype(np.complex128).reshape(X.shape[0] * 2, 3 * npts).T     # one column per half
+    ref = prob.precond(cols, sigma).T.reshape(X.shape)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"   rel err {err:.2e}")
+    assert err < 2e-6
 
 
 def test_apply_rejects_bad_arguments():

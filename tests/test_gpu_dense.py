@@ -134,6 +134,35 @@ def test_jacobi_svd_real_matches_numpy(rows, m, spread):
     ctx.close()
 
 
+# A real Jacobi round shares each column-block pair among BDG_JACOBI_SPLIT workgroups (8 by
+# default), each computing the pair's rotation and rotating a share of the rows, the rounds
+# alternating between two buffers; with 1 the pair's workgroup works in place.  Same
+# rotations and the same arithmetic per row: the two must agree bit for bit (odd and even
+# numbers of rounds, ragged blocks, more rows than columns and fewer).
+@pytest.mark.parametrize("rows,m", [(240, 240), (161, 161), (37, 24), (17, 33)])
+def test_jacobi_svd_real_split_matches_single(rows, m, monkeypatch):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"svd real split vs single {rows}x{m}")
+    rng = np.random.default_rng(12)
+    kk = min(rows, m)
+    Ua, _ = np.linalg.qr(rng.standard_normal((rows, kk)))
+    Va, _ = np.linalg.qr(rng.standard_normal((m, kk)))
+    Gm = (Ua * np.logspace(0.0, -3.6, kk)) @ Va.T
+    out = {}
+    for split in ("1", "8"):
+        monkeypatch.setenv("BDG_JACOBI_SPLIT", split)
+        ctx = _ctx()
+        Gd = torch.from_numpy(Gm.T.astype(np.complex128).copy()).cuda()
+        V = torch.zeros((m, m), dtype=torch.complex128, device="cuda")
+        s = torch.zeros(m, dtype=torch.float64, device="cuda")
+        assert ctx._lib.bdg_test_svd_real(ctx._h, rows, m, _p(Gd), rows, _p(V), m, _p(s)) == _lib.BDG_OK
+        out[split] = (Gd.cpu().numpy(), V.cpu().numpy(), s.cpu().numpy())
+        ctx.close()
+    for a, b in zip(out["1"], out["8"]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("m", [1, 5, 64, 240])
 def test_cholesky_matches_numpy(m):
     torch = torch_cuda()
