@@ -60,13 +60,14 @@ bool debug_on() {
     return v == 1;
 }
 
-// BDG_UPDATE_FUSE=0 takes the two-launch basis update
-bool update_fuse_enabled() {
+// the basis update: one pass in both phases (2, the default); BDG_UPDATE_FUSE=1 keeps the
+// two launches in the float32 phase, 0 everywhere
+int update_fuse_mode() {
     static const int v = [] {
         const char* e = std::getenv("BDG_UPDATE_FUSE");
-        return (e && e[0] == '0') ? 0 : 1;
+        return e ? std::atoi(e) : 2;
     }();
-    return v == 1;
+    return v;
 }
 
 // runs a callable when the scope ends (workspace release on every return path)
@@ -1310,14 +1311,15 @@ bdg_status eigs_impl(bdg_ctx* c, int k, int nb_req, double tol, int max_iter, co
         if (rst != BDG_OK) { final_status = rst; break; }
         BDG_TRY(mark(4));
         // updates: P_new = [W, P] a[nb:] into the free slot and F_new = F a[:nb] + P_new into
-        // W's slot.  With float64 images, blocks of up to 96 real columns take one fused
-        // launch per array, which reads F, W and P once and writes both (F_new over W's rows
-        // is row-local); otherwise two launches, P_new first, so that no output overlaps an
-        // input.  The float32 phase keeps the two launches: the two forms differ in rounding
-        // order only, and that phase is sensitive to it (measured on the 3-D trap, the one-pass
-        // form's trajectory left the float32 phase at iteration 41 instead of 80)
+        // W's slot.  Blocks of up to 96 real columns take one fused launch per array, which
+        // reads F, W and P once and writes both (F_new over W's rows is row-local); otherwise
+        // two launches, P_new first, so that no output overlaps an input.  The two forms
+        // differ in rounding order only; the float32 phase's trajectory is sensitive to such
+        // differences (on an earlier state of this solver the one-pass form made it end at
+        // iteration 41 instead of 80; on the current one it does not)
         const int dst_P = S.slotFree, dst_F = S.slotW;
-        const bool fuse = nb <= 96 && nbc % 8 == 0 && !w32img && update_fuse_enabled();
+        const int fmode = update_fuse_mode();
+        const bool fuse = nb <= 96 && nbc % 8 == 0 && ((!w32img && fmode >= 1) || fmode == 2);
         for (int a = 0; a < 4; ++a) {
             const Seg* seg = (a == SF) ? sf : (a == SG) ? sg : (a == HSF) ? hf : hg;
             const double2* coef = (a == SF || a == HSF) ? acoef : bcoef;
