@@ -697,7 +697,7 @@ def main():
     a_gbs = a_bytes / (a_ms * 1e-3) / 1e9
     roof = {"bound": "mfma", "achieved": round(g_tfs, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
             "frac": round(g_tfs / FP64_MFMA_PEAK_TFS, 4), "traffic": _traffic("gram", w.name),
-            "kernel": f"k_gram_pair_w8d + k_gram_reduce_real: Rayleigh-Ritz Gram S^T (H S) of {3 * w.block} real "
+            "kernel": f"k_gram_pair_w8d + k_gram_reduce_real_st: Rayleigh-Ritz Gram S^T (H S) of {3 * w.block} real "
                       f"columns (paired, {3 * w.block // 2} complex) x {3 * w.npts} rows, FP64 MFMA",
             "ms_per_launch": round(g_ms, 3), "algorithmic_flops": g_flops}
     roof_apply = {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

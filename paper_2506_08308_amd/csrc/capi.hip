@@ -263,6 +263,7 @@ bdg_status bdg_create(const bdg_problem* pr, const double* V_dev, void* hip_stre
     if (const char* e = std::getenv("BDG_GRAM_WIDE")) c->gram_wide = e[0] != '0';
     if (const char* e = std::getenv("BDG_GRAM_W8")) c->gram_w8 = std::atoi(e);
     if (const char* e = std::getenv("BDG_JACOBI_SPLIT")) c->jacobi_split = std::max(1, std::min(8, std::atoi(e)));
+    if (const char* e = std::getenv("BDG_DEEP_LOADS")) c->deep_loads = e[0] != '0';
     c->dim = pr->dim;
     c->npts = 1;
     c->hd = 1.0;

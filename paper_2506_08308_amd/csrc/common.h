@@ -84,6 +84,10 @@ struct bdg_ctx {
     int gram_w8 = 2;              // ... in blocks of 8 complex columns (2: operands loaded straight to
                                   // LDS, 1: staged through registers, 0: off)
     int jacobi_split = 8;         // workgroups per column-block pair in a real Jacobi round
+    // deeper staging of the loads (the same bits as the plain forms) in the split-K
+    // reductions of the Grams, Grams of at most 16 x 16 and updates of at most 8 into 16
+    // columns
+    bool deep_loads = true;
     // scratch owned by the context (grown on demand)
     DevBuf scratch[9];
     // caller-provided workspace: while `base` is set, ctx_alloc and ctx_scratch hand out

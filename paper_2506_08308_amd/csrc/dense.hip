@@ -898,6 +898,105 @@ __global__ void __launch_bounds__(256) k_gram_thin(long long K, int m1, int m2, 
     }
 }
 
+// Thin Gram of at most 16 x 16 (dot products, projections onto one or two vectors) with deep
+// staging.  k_gram_thin moves one 16-row chunk per pair of barriers; with m1 + m2 of two
+// columns that is 512 bytes per workgroup in flight, a tenth of the bandwidth of the chip,
+// and its one computing wave puts the matrix-core work of a CU on one SIMD.  Here a
+// workgroup takes four K-splits, wave v the accumulator chain of split 4 w + v, and stages ds
+// chunks of all four at once, the loads of the next ds chunks in flight while the waves
+// execute the matrix-core steps of the current ones.  Split boundaries, chunk order, the
+// operands of every MFMA and the accumulator chain are those of k_gram_thin (the zero padding
+// of columns and rows included), so the partials are the same bits.  LDS: 4 splits x ds
+// chunks x (m1 + m2) columns x GPAD doubles, A's columns first; a stage is THIN_TI items (one
+// row of one column) per thread, two groups of 256 per split, rows fastest.
+constexpr int THIN_TI = 8;
+
+__global__ void __launch_bounds__(256) k_gram_thin_deep(long long K, int m1, int m2, SegList A, long long lda,
+                                                        SegList B, long long ldb, long long kper, int ds,
+                                                        long long nsplit, long long total, long long per_xcd,
+                                                        double2* __restrict__ part) {
+    extern __shared__ __align__(16) double lds_thin[];
+    const long long L = blockIdx.x;
+    const long long w = (L & 7) * per_xcd + (L >> 3);
+    if (w >= total) return;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int nc = m1 + m2;
+    const int srows = ds * GKC;                 // rows per stage and split
+    const int items = srows * nc;               // items per stage and split (<= 512)
+    const int region = ds * nc * GPAD;          // doubles per split in LDS
+    // the four splits' row ranges (an empty one past the last split)
+    auto krange = [&](int v, long long* a, long long* e) {
+        const long long sp = 4 * w + v;
+        *a = sp < nsplit ? sp * kper : K;
+        *e = sp < nsplit ? min(*a + kper, K) : K;
+    };
+    double2 rv[THIN_TI];
+    auto gload = [&](long long off) {
+#pragma unroll
+        for (int u = 0; u < THIN_TI; ++u) {
+            const int v = u >> 1;
+            const int i = (u & 1) * 256 + t;
+            const int col = i / srows, r = i - col * srows;
+            long long a, e;
+            krange(v, &a, &e);
+            const long long kk = a + off + r;
+            rv[u] = double2{0, 0};
+            if (i < items && kk < e)
+                rv[u] = col < m1 ? seg_col(A, col, lda)[kk] : seg_col(B, col - m1, ldb)[kk];
+        }
+    };
+    const bool odd = (lane >> 4) & 1;
+    const int ci = lane & 15;
+    long long ka, ke;
+    krange(wave, &ka, &ke);
+    d4 accr = d4{0, 0, 0, 0}, acci = d4{0, 0, 0, 0};
+    gload(0);
+    for (long long off = 0; off < kper; off += srows) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < THIN_TI; ++u) {
+            const int v = u >> 1;
+            const int i = (u & 1) * 256 + t;
+            if (i < items) {
+                const int col = i / srows, r = i - col * srows;
+                const int j = r / GKC, lk = r - j * GKC;
+                *reinterpret_cast<double2*>(&lds_thin[v * region + (j * nc + col) * GPAD + 2 * lk]) = rv[u];
+            }
+        }
+        __syncthreads();
+        if (off + srows < kper) gload(off + srows);
+        for (int j = 0; j < ds && ka + off + (long long)j * GKC < ke; ++j) {
+            const double* la = lds_thin + wave * region + (j * nc) * GPAD;
+            const double* lb = la + m1 * GPAD;
+#pragma unroll
+            for (int ks = 0; ks < GKR; ks += 4) {
+                const int kr = ks + (lane >> 4);
+                const int kp = ks + ((lane >> 4) & 2);
+                const double2 pa = ci < m1 ? *reinterpret_cast<const double2*>(&la[ci * GPAD + kp]) : double2{0, 0};
+                const double a = odd ? pa.y : pa.x;
+                const double ap = odd ? pa.x : -pa.y;
+                const double b = ci < m2 ? lb[ci * GPAD + kr] : 0.0;
+                accr = mfma(a, b, accr);
+                acci = mfma(ap, b, acci);
+            }
+        }
+    }
+    const long long sp = 4 * w + wave;
+    if (sp >= nsplit) return;
+    double2* out = part + sp * m1 * m2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = 4 * r + (lane >> 4);
+        if (p < m1 && ci < m2) {
+            double2 v;
+            v.x = accr[r];
+            v.y = acci[r];
+            out[(long long)ci * m1 + p] = v;
+        }
+    }
+}
+
 // C = alpha * sum_s part[s] (fixed order); Hermitian: fill the lower triangle from the upper.
 __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restrict__ part, double alpha,
                               double2* __restrict__ C, int ldc, int herm) {
@@ -931,6 +1030,102 @@ __global__ void k_gram_reduce(int m1, int m2, int nsplit, const double2* __restr
     o.x = alpha * sx;
     o.y = mirror ? -alpha * sy : alpha * sy;
     C[(long long)q * ldc + p] = o;
+}
+
+// The split-K reductions above give each entry one thread, which walks the splits with eight
+// loads in flight: with few entries (a dot product, a projection onto two vectors) that is
+// a few kilobytes in flight for the whole chip, and a reduction of 2500 splits takes 100 us.
+// The staged form: a workgroup per G consecutive entries (G a power of two, G <= 64) stages
+// the partials of RED_BYTES / (G sizeof(T)) splits at a time in LDS, every thread loading one
+// entry's values at a stride of 256 / G splits, and thread e < G then adds up its entry's
+// staged values in split order: the additions of the one-thread form in the same order, so
+// the same bits.  The loads of the next splits are in flight while the sums run.
+constexpr int RED_BYTES = 32768;
+
+template <typename T>
+__device__ __forceinline__ void red_add(T& a, const T& v) {
+    if constexpr (std::is_same<T, double>::value) a += v;
+    else { a.x += v.x; a.y += v.y; }
+}
+
+// sums over the splits of entry e0 + (t & (G - 1)) into *acc (threads t < G); off: offset of
+// the thread's entry in a split's plane, live: whether it takes part
+template <typename T>
+__device__ __forceinline__ void staged_sum(int nsplit, const T* __restrict__ part, long long plane, long long off,
+                                           bool live, int G, T* acc) {
+    extern __shared__ __align__(16) unsigned char red_raw[];
+    T* lred = reinterpret_cast<T*>(red_raw);
+    constexpr int NI = RED_BYTES / (int)sizeof(T) / 256;      // staged values per thread
+    const int t = threadIdx.x;
+    const int sc = RED_BYTES / (int)sizeof(T) / G;          // splits per stage
+    const int s_t = t / G, s_step = 256 / G;
+    T rv[NI];
+    auto gload = [&](int s0) {
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int sp = s0 + s_t + u * s_step;
+            rv[u] = T{};
+            if (live && sp < nsplit) rv[u] = part[(long long)sp * plane + off];
+        }
+    };
+    T a{};
+    gload(0);
+    for (int s0 = 0; s0 < nsplit; s0 += sc) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NI; ++u) lred[t + 256 * u] = rv[u];
+        __syncthreads();
+        if (s0 + sc < nsplit) gload(s0 + sc);
+        if (t < G) {
+            const int cnt = min(sc, nsplit - s0);
+#pragma unroll 8
+            for (int j = 0; j < cnt; ++j) red_add(a, lred[j * G + t]);
+        }
+    }
+    *acc = a;
+}
+
+__global__ void __launch_bounds__(256) k_gram_reduce_st(int m1, int m2, int nsplit, const double2* __restrict__ part,
+                                                        double alpha, double2* __restrict__ C, int ldc, int herm,
+                                                        int G) {
+    const long long tot = (long long)m1 * m2;
+    const long long idx = (long long)blockIdx.x * G + (threadIdx.x & (G - 1));
+    const bool live = idx < tot;
+    int p = 0, q = 0;
+    bool mirror = false;
+    long long off = 0;
+    if (live) {
+        p = (int)(idx % m1);
+        q = (int)(idx / m1);
+        mirror = herm && (p / 16) > (q / 16);
+        off = (long long)(mirror ? p : q) * m1 + (mirror ? q : p);
+    }
+    double2 sum;
+    staged_sum<double2>(nsplit, part, tot, off, live, G, &sum);
+    if ((int)threadIdx.x >= G || !live) return;
+    double2 o;
+    o.x = alpha * sum.x;
+    o.y = mirror ? -alpha * sum.y : alpha * sum.y;
+    C[(long long)q * ldc + p] = o;
+}
+
+__global__ void __launch_bounds__(256) k_gram_reduce_real_st(int m1, int m2, int nsplit,
+                                                             const double* __restrict__ part, double alpha,
+                                                             double2* __restrict__ C, int ldc, int herm, int G) {
+    const long long tot = (long long)m1 * m2;
+    const long long idx = (long long)blockIdx.x * G + (threadIdx.x & (G - 1));
+    int p = 0, q = 0;
+    bool live = idx < tot;
+    if (live) {
+        p = (int)(idx % m1);
+        q = (int)(idx / m1);
+        live = !(herm && (p / 16) > (q / 16));
+    }
+    double sum;
+    staged_sum<double>(nsplit, part, tot, (long long)q * m1 + p, live, G, &sum);
+    if ((int)threadIdx.x >= G || !live) return;
+    C[(long long)q * ldc + p] = double2{alpha * sum, 0.0};
+    if (herm && (p / 16) < (q / 16)) C[(long long)p * ldc + q] = double2{alpha * sum, 0.0};
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1081,6 +1276,79 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         if (FUSE && it == nwp - 1) store(Y2, ldy2, false);   // P_new; F's chunks follow
     }
     store(Y, ldy, !FUSE);
+}
+
+// Update of at most 8 columns of S into at most 16 columns of Y (projections onto one or two
+// vectors, dot-product sized work): one chunk of S, one column tile.  k_update spends a
+// workgroup of 256 threads on 64 rows, and with one column that is 3 KB of traffic per
+// workgroup, bound by the workgroup launch rate.  Here each wave walks UPD_UB row blocks of
+// 16 at a time (all loads first) with the coefficients in registers, and executes for every
+// block the MFMAs of k_update<1, 1, false> in the same order on the same operands (the zero
+// padding of columns and rows included), so Y is the same bits.  Y may alias Z, or S within
+// the same rows (a wave reads all its rows before it writes them).
+constexpr int UPD_UB = 4;
+
+__global__ void __launch_bounds__(256) k_update_thin(long long K, SegList segs, long long lds, int m,
+                                                     const double2* __restrict__ Cm, int ldcm, int nb, double beta,
+                                                     const double2* Z, long long ldz, double2* Y, long long ldy) {
+    const int lane = threadIdx.x & 63;
+    const int ri = lane & 15, kq = lane >> 4;
+    // MFMA step s takes columns l = 4 s + kq of S and rows l of C, C(l, ri) on lane (ri, kq)
+    double2 cv[2], cw[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int l = 4 * s + kq;
+        cv[s] = (l < m && ri < nb) ? Cm[(long long)ri * ldcm + l] : double2{0, 0};
+        cw[s] = double2{-cv[s].y, cv[s].x};
+    }
+    const double2* scol[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) scol[s] = 4 * s + kq < m ? seg_col(segs, 4 * s + kq, lds) : nullptr;
+    const long long nrb = (K + 15) / 16;
+    const long long nw = (long long)gridDim.x * 4;
+    for (long long rb0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * UPD_UB; rb0 < nrb; rb0 += nw * UPD_UB) {
+        double2 sv[UPD_UB][2];
+#pragma unroll
+        for (int u = 0; u < UPD_UB; ++u) {
+            const long long row = (rb0 + u) * 16 + ri;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) sv[u][s] = (scol[s] && row < K) ? scol[s][row] : double2{0, 0};
+        }
+        double2 zv[UPD_UB][4];
+#pragma unroll
+        for (int u = 0; u < UPD_UB; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = (rb0 + u) * 16 + 4 * r + kq;
+                zv[u][r] = (beta != 0.0 && ri < nb && row < K) ? Z[(long long)ri * ldz + row] : double2{0, 0};
+            }
+#pragma unroll
+        for (int u = 0; u < UPD_UB; ++u) {
+            d4 accr = d4{0, 0, 0, 0}, acci = d4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                accr = mfma(sv[u][s].x, cv[s].x, accr);
+                acci = mfma(sv[u][s].x, cv[s].y, acci);
+                accr = mfma(sv[u][s].y, cw[s].x, accr);
+                acci = mfma(sv[u][s].y, cw[s].y, acci);
+            }
+            if (ri >= nb) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = (rb0 + u) * 16 + 4 * r + kq;
+                if (row >= K) continue;
+                double2 v;
+                v.x = accr[r];
+                v.y = acci[r];
+                if (beta != 0.0) {
+                    const double2 o = zv[u][r];
+                    v.x += beta * o.x;
+                    v.y += beta * o.y;
+                }
+                Y[(long long)ri * ldy + row] = v;
+            }
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1275,6 +1543,42 @@ static bool make_seglist(const Seg* segs, int nseg, SegList* sl, int* m) {
 // workgroups resident on the device at once (slots), so that the last round is not left
 // partly empty; at least 512 rows per split; at most max_split splits (0: no cap).
 // Returns the rows per split (a multiple of GKC).
+// C = alpha * (sum over the nsplit partials in ws), by the staged or the one-thread form (the
+// same bits); complex partials of the complex Grams, real ones of the paired Grams
+static int reduce_group(long long tot) {
+    int G = 1;
+    while (G < 64 && 2LL * G * 128 <= tot) G *= 2;
+    return G;
+}
+
+static bdg_status gram_reduce(bdg_ctx* c, int m1, int m2, long long nsplit, const void* ws, double alpha,
+                              double2* C, int ldc, int herm) {
+    const long long tot = (long long)m1 * m2;
+    if (c->deep_loads) {
+        const int G = reduce_group(tot);
+        hipLaunchKernelGGL(k_gram_reduce_st, dim3((unsigned)((tot + G - 1) / G)), dim3(256), RED_BYTES, c->stream,
+                           m1, m2, (int)nsplit, (const double2*)ws, alpha, C, ldc, herm, G);
+    } else {
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,
+                           (int)nsplit, (const double2*)ws, alpha, C, ldc, herm);
+    }
+    return hip_check(c, hipGetLastError(), "k_gram_reduce");
+}
+
+static bdg_status gram_reduce_real(bdg_ctx* c, int r1, int r2, long long nsplit, const void* ws, double alpha,
+                                   double2* C, int ldc, int herm) {
+    const long long tot = (long long)r1 * r2;
+    if (c->deep_loads) {
+        const int G = reduce_group(tot);
+        hipLaunchKernelGGL(k_gram_reduce_real_st, dim3((unsigned)((tot + G - 1) / G)), dim3(256), RED_BYTES,
+                           c->stream, r1, r2, (int)nsplit, (const double*)ws, alpha, C, ldc, herm, G);
+    } else {
+        hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, r1, r2,
+                           (int)nsplit, (const double*)ws, alpha, C, ldc, herm);
+    }
+    return hip_check(c, hipGetLastError(), "k_gram_reduce_real");
+}
+
 static long long gram_rows_per_split(long long K, long long items, long long slots, long long* nsplit,
                                      long long max_split) {
     const long long rounds = std::max<long long>(1, (2048 + slots / 2) / slots);
@@ -1318,13 +1622,21 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         BDG_TRY(ctx_scratch(c, 0, (size_t)nsplit * m1 * m2 * sizeof(double2), &ws));
         const long long total = nsplit * ncg;
         const long long per_xcd = (total + 7) / 8;
-        hipLaunchKernelGGL(k_gram_thin, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda,
-                           B, ldb, kper, ncg, total, per_xcd, (double2*)ws);
+        if (c->deep_loads && m2 <= 16) {
+            // the same partials from deeper staging (ncg == 1): four splits per workgroup, ds
+            // chunks per stage, at most 512 items per split and stage
+            const int ds = THIN_TI * 64 / (GKC * (m1 + m2));
+            const long long wgs = (nsplit + 3) / 4;
+            const long long pxd = (wgs + 7) / 8;
+            const size_t lds = (size_t)4 * ds * (m1 + m2) * GPAD * sizeof(double);
+            hipLaunchKernelGGL(k_gram_thin_deep, dim3((unsigned)(8 * pxd)), dim3(256), lds, c->stream, K, m1, m2,
+                               A, lda, B, ldb, kper, ds, nsplit, wgs, pxd, (double2*)ws);
+        } else {
+            hipLaunchKernelGGL(k_gram_thin, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A,
+                               lda, B, ldb, kper, ncg, total, per_xcd, (double2*)ws);
+        }
         BDG_HIP(c, hipGetLastError());
-        const long long tot = (long long)m1 * m2;
-        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,
-                           (int)nsplit, (const double2*)ws, alpha, C, ldc, hermitian ? 1 : 0);
-        return hip_check(c, hipGetLastError(), "k_gram_thin");
+        return gram_reduce(c, m1, m2, nsplit, ws, alpha, C, ldc, hermitian ? 1 : 0);
     }
     const bool t80 = 25 * 264 * tiles(80) < 16 * 204 * tiles(64);
     const int edge = t80 ? 80 : GT;
@@ -1348,10 +1660,7 @@ bdg_status gram_seg(bdg_ctx* c, long long K, const Seg* sa, int na, long long ld
         hipLaunchKernelGGL(k_gram, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda, B,
                            ldb, kper, tn, h, sm, ntiles, total, per_xcd, (double2*)ws);
     BDG_HIP(c, hipGetLastError());
-    const long long tot = (long long)m1 * m2;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m1, m2,
-                       (int)nsplit, (const double2*)ws, alpha, C, ldc, h);
-    return hip_check(c, hipGetLastError(), "k_gram");
+    return gram_reduce(c, m1, m2, nsplit, ws, alpha, C, ldc, h);
 }
 
 template <>
@@ -1373,6 +1682,15 @@ bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long l
     SegList sl;
     int m = 0;
     if (!make_seglist(segs, nseg, &sl, &m)) return ctx_fail(c, BDG_EINVAL, "update: 1..4 segments");
+    if (c->deep_loads && m <= 8 && nb <= 16) {
+        // the same bits from a row loop per wave (see k_update_thin)
+        const long long nrb = (K + 15) / 16;
+        const long long wg = std::max<long long>(1, std::min<long long>((nrb + 4 * UPD_UB - 1) / (4 * UPD_UB),
+                                                                        4LL * c->ncu));
+        hipLaunchKernelGGL(k_update_thin, dim3((unsigned)wg), dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb,
+                           beta, Z, ldz, Y, ldy);
+        return hip_check(c, hipGetLastError(), "k_update_thin");
+    }
     const int cb = std::min(5, (nb + 15) / 16);
     const int ctiles = (nb + 16 * cb - 1) / (16 * cb);
     // 16 rows per wave (RA = 1): 10 accumulator tiles per wave leave room for two waves per
@@ -1430,10 +1748,7 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
             hipLaunchKernelGGL(k_gram_pair_wide, dim3((unsigned)nsplit), dim3(512), 0, c->stream, K, m1, m2,
                                hermitian ? 1 : 0, A, lda, B, ldb, kper, same ? 1 : 0, (double*)ws);
         BDG_HIP(c, hipGetLastError());
-        const long long tot = r1 * r2;
-        hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, (int)r1,
-                           (int)r2, (int)nsplit, (const double*)ws, alpha, C, ldc, hermitian ? 1 : 0);
-        return hip_check(c, hipGetLastError(), "k_gram_pair_wide");
+        return gram_reduce_real(c, (int)r1, (int)r2, nsplit, ws, alpha, C, ldc, hermitian ? 1 : 0);
     }
     const int tm = (m1 + GT - 1) / GT, tn = (m2 + GT - 1) / GT;
     const int ntiles = hermitian ? tn * (tn + 1) / 2 : tm * tn;
@@ -1447,10 +1762,7 @@ bdg_status gram_seg_pair(bdg_ctx* c, long long K, const Seg* sa, int na, long lo
     hipLaunchKernelGGL(k_gram_pair, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, c->stream, K, m1, m2, A, lda, B, ldb,
                        kper, tn, h, sm, ntiles, total, per_xcd, (double*)ws);
     BDG_HIP(c, hipGetLastError());
-    const long long tot = r1 * r2;
-    hipLaunchKernelGGL(k_gram_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, (int)r1,
-                       (int)r2, (int)nsplit, (const double*)ws, alpha, C, ldc, h);
-    return hip_check(c, hipGetLastError(), "k_gram_pair");
+    return gram_reduce_real(c, (int)r1, (int)r2, nsplit, ws, alpha, C, ldc, h);
 }
 
 bdg_status update_pair(bdg_ctx* c, long long K, const Seg* segs, int nseg, long long lds, const double2* Cr, int ldcr,

@@ -58,7 +58,8 @@ def test_gram_matches_numpy(K, m1, m2, herm):
 
 
 @pytest.mark.parametrize("K,m,nb,beta", [(37, 5, 3, 0.0), (1000, 40, 16, 0.0), (5000, 240, 80, 1.0),
-                                         (129, 7, 33, -0.5), (100000, 24, 8, 0.0)])
+                                         (129, 7, 33, -0.5), (100000, 24, 8, 0.0), (100003, 1, 1, 1.0),
+                                         (4099, 8, 16, -0.5)])
 def test_update_matches_numpy(K, m, nb, beta):
     torch = torch_cuda()
     from paper_2506_08308_amd import _lib
@@ -292,6 +293,82 @@ def test_gram_pair_w8_direct_matches_staged(K, m1, m2, sym, monkeypatch):
         out[mode] = C.cpu().numpy()
         ctx.close()
     assert np.array_equal(out["1"], out["2"])
+
+
+# Deeper staging of the loads (thin Grams of at most 16 x 16, the split-K reductions of every
+# Gram) against the plain forms: the same K-splits, chunk order, matrix-core operands and
+# order of additions, so the two agree bit for bit.  The solver's dot products over
+# 3 x 128^3 rows, projections onto one or two vectors, the 64- and 80-tilings, Hermitian
+# mirrors and ragged tails.
+@pytest.mark.parametrize("K,m1,m2,herm", [(6291456, 1, 1, 0), (6291456, 1, 1, 1), (6291456, 2, 1, 0),
+                                          (1000003, 1, 2, 0), (70001, 16, 3, 0), (9000, 12, 12, 1),
+                                          (37, 5, 7, 0), (100003, 16, 16, 0), (4099, 3, 16, 0),
+                                          (200000, 2, 40, 0), (100000, 240, 240, 1), (5000, 80, 120, 0),
+                                          (20000, 144, 144, 1)])
+def test_deep_loads_gram_matches_plain(K, m1, m2, herm, monkeypatch):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"gram deep loads vs plain K={K} {m1}x{m2} herm={herm}")
+    Ad = torch.from_numpy(W.random_block((m1, K), seed=4)).cuda()
+    Bd = Ad if herm else torch.from_numpy(W.random_block((m2, K), seed=5)).cuda()
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BDG_DEEP_LOADS", mode)
+        ctx = _ctx()
+        C = torch.zeros((m2, m1), dtype=torch.complex128, device="cuda")
+        st = ctx._lib.bdg_test_gram(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 0.5, _p(C), m1, herm)
+        assert st == _lib.BDG_OK
+        out[mode] = C.cpu().numpy()
+        ctx.close()
+    assert np.array_equal(out["0"].view(np.uint64), out["1"].view(np.uint64))
+    ref = 0.5 * (Ad.cpu().numpy().conj() @ Bd.cpu().numpy().T)
+    assert np.abs(out["1"].T - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# The paired Grams' split-K reductions, staged and plain: the same bits (the 8-column, wide
+# and 64-tile forms).
+@pytest.mark.parametrize("K,m1,m2,sym", [(20000, 120, 120, 1), (30011, 33, 100, 0), (100003, 40, 40, 1),
+                                         (4099, 128, 128, 1), (777, 97, 97, 0)])
+def test_deep_loads_gram_pair_matches_plain(K, m1, m2, sym, monkeypatch):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"gram pair deep loads vs plain K={K} {m1}x{m2} sym={sym}")
+    Ad = torch.from_numpy(W.random_block((m1, K), seed=1)).cuda()
+    Bd = Ad if sym else torch.from_numpy(W.random_block((m2, K), seed=2)).cuda()
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BDG_DEEP_LOADS", mode)
+        ctx = _ctx()
+        C = torch.zeros((2 * m2, 2 * m1), dtype=torch.complex128, device="cuda")
+        st = ctx._lib.bdg_test_gram_pair(ctx._h, K, m1, m2, _p(Ad), K, _p(Bd), K, 1.0, _p(C), 2 * m1, sym)
+        assert st == _lib.BDG_OK
+        out[mode] = C.cpu().numpy()
+        ctx.close()
+    assert np.array_equal(out["0"].view(np.uint64), out["1"].view(np.uint64))
+
+
+# Updates of at most 8 into 16 columns by a row loop per wave: the MFMAs of the general
+# form on the same operands, so the two agree bit for bit (projections of one vector onto
+# one or two over 3 x 128^3 rows, beta 0 and not, ragged row tails).
+@pytest.mark.parametrize("K,m,nb,beta", [(6291456, 1, 1, 1.0), (6291456, 2, 1, 1.0), (1000003, 8, 16, 0.0),
+                                         (37, 5, 3, 0.5), (100003, 3, 7, -1.0), (5, 1, 1, 1.0)])
+def test_update_thin_matches_general(K, m, nb, beta, monkeypatch):
+    torch = torch_cuda()
+    from paper_2506_08308_amd import _lib
+    say(f"update thin vs general K={K} m={m} nb={nb} beta={beta}")
+    Sd = torch.from_numpy(W.random_block((m, K), seed=6)).cuda()
+    Cd = torch.from_numpy(W.random_block((nb, m), seed=7)).cuda()
+    Y0 = torch.from_numpy(W.random_block((nb, K), seed=8)).cuda()
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BDG_DEEP_LOADS", mode)
+        ctx = _ctx()
+        Yd = Y0.clone()
+        st = ctx._lib.bdg_test_update(ctx._h, K, m, _p(Sd), K, _p(Cd), m, nb, beta, _p(Yd), K)
+        assert st == _lib.BDG_OK
+        out[mode] = Yd.cpu().numpy()
+        ctx.close()
+    assert np.array_equal(out["0"].view(np.uint64), out["1"].view(np.uint64))
 
 
 # One-pass update of the eigensolver (F columns first): the solve's shape, a ragged row tail,
