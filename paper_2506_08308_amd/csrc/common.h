@@ -85,8 +85,8 @@ struct bdg_ctx {
                                   // LDS, 1: staged through registers, 0: off)
     int jacobi_split = 8;         // workgroups per column-block pair in a real Jacobi round
     // deeper staging of the loads (the same bits as the plain forms) in the split-K
-    // reductions of the Grams, Grams of at most 16 x 16 and updates of at most 8 into 16
-    // columns
+    // reductions of the Grams, Grams of at most 16 x 16 and updates of at most 8 columns
+    // into at most 48
     bool deep_loads = true;
     // scratch owned by the context (grown on demand)
     DevBuf scratch[9];

@@ -1148,7 +1148,11 @@ __global__ void __launch_bounds__(256) k_gram_reduce_real_st(int m1, int m2, int
 // accumulators: it visits the [W, P] chunks first, stores Y2 from the accumulators, and goes
 // on with the F chunks.  Y may alias an input of the same rows: a workgroup reads all its
 // input rows before it writes its output rows, and owns all output columns of its rows.
-template <int CB, int RA, bool PAIR, bool FUSE = false>
+// ZPRE (plain form, one chunk of S, beta != 0, CB <= 3): the workgroup loads its Z
+// elements first, so that their latency overlaps the loads and MFMAs of S C instead of
+// following them (the projections of a block onto a few vectors, X -= Q (Q^H X)).  The same
+// bits.
+template <int CB, int RA, bool PAIR, bool FUSE = false, bool ZPRE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(long long K, SegList segs, long long lds, int m,
                                                 const double2* __restrict__ Cm, int ldcm, int nb, double beta,
                                                 const double2* Z, long long ldz, double2* Y, long long ldy,
@@ -1199,6 +1203,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             if (idx < CR * NC && lc < lend && j0 + j < nb) rc[u] = Cm[(long long)(j0 + j) * ldcm + row];
         }
     };
+    double2 zp[ZPRE ? RA : 1][ZPRE ? CB : 1][4];
+    if constexpr (ZPRE) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const int j = j0 + 16 * b + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const long long row = R0 + wr + 16 * a + 4 * r + (lane >> 4);
+                    zp[a][b][r] = (j < nb && row < K) ? Z[(long long)j * ldz + row] : double2{0, 0};
+                }
+            }
+    }
     // accumulators -> Yo (plus beta Z in the plain form)
     auto store = [&](double2* Yo, long long ldo, bool with_z) {
 #pragma unroll
@@ -1215,7 +1233,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     v.x = accr[a][b][r];
                     v.y = acci[a][b][r];
                     if (with_z && beta != 0.0) {
-                        const double2 o = Z[(long long)j * ldz + row];
+                        double2 o;
+                        if constexpr (ZPRE) o = zp[a][b][r];
+                        else o = Z[(long long)j * ldz + row];
                         v.x += beta * o.x;
                         v.y += beta * o.y;
                     }
@@ -1697,16 +1717,27 @@ bdg_status update_add(bdg_ctx* c, long long K, const Seg* segs, int nseg, long l
     // SIMD, measured 25 % faster on the 3-D solve than 32 rows per wave
     constexpr int RA = 1;
     dim3 grid((unsigned)((K + 64 * RA - 1) / (64 * RA)), (unsigned)ctiles);
+    // one chunk of S and a Z term over at most 48 columns: Z loaded first (k_update's ZPRE;
+    // measured 7 % faster on 2 into 40 columns, and twice as slow at 80 columns, where the
+    // prefetched Z no longer fits three waves)
+    const bool zpre = c->deep_loads && m <= 8 && beta != 0.0;
 #define BDG_UPD(CBV) \
     hipLaunchKernelGGL((k_update<CBV, RA, false>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, ldcm, nb, beta, Z, ldz, Y, ldy, \
                        0, (double2*)nullptr, 0LL)
+#define BDG_UPDZ(CBV) \
+    if (zpre) \
+        hipLaunchKernelGGL((k_update<CBV, RA, false, false, true>), grid, dim3(256), 0, c->stream, K, sl, lds, m, Cm, \
+                           ldcm, nb, beta, Z, ldz, Y, ldy, 0, (double2*)nullptr, 0LL); \
+    else \
+        BDG_UPD(CBV)
     switch (cb) {
-        case 1: BDG_UPD(1); break;
-        case 2: BDG_UPD(2); break;
-        case 3: BDG_UPD(3); break;
+        case 1: BDG_UPDZ(1); break;
+        case 2: BDG_UPDZ(2); break;
+        case 3: BDG_UPDZ(3); break;
         case 4: BDG_UPD(4); break;
         default: BDG_UPD(5); break;
     }
+#undef BDG_UPDZ
 #undef BDG_UPD
     return hip_check(c, hipGetLastError(), "k_update");
 }

@@ -347,11 +347,14 @@ def test_deep_loads_gram_pair_matches_plain(K, m1, m2, sym, monkeypatch):
     assert np.array_equal(out["0"].view(np.uint64), out["1"].view(np.uint64))
 
 
-# Updates of at most 8 into 16 columns by a row loop per wave: the MFMAs of the general
-# form on the same operands, so the two agree bit for bit (projections of one vector onto
-# one or two over 3 x 128^3 rows, beta 0 and not, ragged row tails).
+# Updates of at most 8 into 16 columns by a row loop per wave, and of at most 8 into more
+# columns with Z loaded first: the MFMAs of the general form on the same operands, so the
+# two agree bit for bit (projections of one vector, or of a block, onto one or two vectors
+# over up to 3 x 128^3 rows, beta 0 and not, ragged row and column tails).
 @pytest.mark.parametrize("K,m,nb,beta", [(6291456, 1, 1, 1.0), (6291456, 2, 1, 1.0), (1000003, 8, 16, 0.0),
-                                         (37, 5, 3, 0.5), (100003, 3, 7, -1.0), (5, 1, 1, 1.0)])
+                                         (37, 5, 3, 0.5), (100003, 3, 7, -1.0), (5, 1, 1, 1.0),
+                                         (1000003, 2, 40, 1.0), (100003, 3, 33, -0.5), (4099, 8, 80, 0.5),
+                                         (37, 5, 17, 1.0)])
 def test_update_thin_matches_general(K, m, nb, beta, monkeypatch):
     torch = torch_cuda()
     from paper_2506_08308_amd import _lib
